@@ -1,0 +1,279 @@
+"""FP64 CPU oracle for the even-odd preconditioned Wilson twisted-mass operator.
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark; never by the library's product path.
+It shares no code with the HIP implementation: the Wilson hop is the plain C
+loop in ``tm_oracle.c`` (built into ``liboracle.so``), everything else here is
+NumPy on canonical full-lattice arrays
+
+    spinor  complex128 [(nrhs,) Lt, Lz, Ly, Lx, nf, 4, 3]
+    links   complex128 [4, Lt, Lz, Ly, Lx, 3, 3]
+
+A field "of parity p" is a full-lattice array that is zero on the other
+parity.
+
+Conventions (the paper leaves them open; the readings are the ones written in
+the design notes):
+  * M = R - kappa * D, i.e. Eq. (2.1) multiplied by 2*kappa with
+    kappa = 1 / (2 m0 + 8), Wilson r = 1.
+  * R = 1 + i a g5 t3 + b t1 with a = 2 kappa mu, b = 2 kappa eps (Eq. 2.1);
+    single flavour: R = 1 +- i a g5 (twist_flavor PLUS / MINUS, Sec. 2.2).
+    Flavour 0 has t3 = +1; t1 swaps the flavours.
+  * g5 = g1 g2 g3 g4 = [[0, 1], [1, 0]] in 2x2 blocks of the basis of Sec. 2.
+  * Preconditioned operators (Eqs. 2.2, 2.3):
+        asym:  R_ee - kappa^2 D_eo R_oo^-1 D_oe
+        sym :  1    - kappa^2 R_ee^-1 D_eo R_oo^-1 D_oe
+  * Right-hand side: b_e + kappa D_eo R_oo^-1 b_o (asym), R_ee^-1 times that
+    (sym).  The printed Eqs. (2.2)/(2.3) omit the kappa, which the kappa^2 of
+    their left-hand side requires once M = R - kappa D.
+  * Odd reconstruction: psi_o = R_oo^-1 (b_o + kappa D_oe psi_e).  The printed
+    Eq. (2.4) has R_ee^-1 psi_e in place of psi_e, which holds only for the
+    right-preconditioned variable R_ee psi_e.
+  * CG: conjugate gradient on the normal equations M^+ M x = M^+ b (the
+    NORMOP solve of Sec. 2.2) in FP64, stopped on the true residual.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile tm_oracle.c with gcc (FP64, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build_oracle()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_hop.argtypes = [dp, dp, dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                              ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.orc_hop.restype = ctypes.c_int
+        L.orc_gammas.argtypes = [dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.complex128 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def gammas() -> np.ndarray:
+    """gamma_mu, mu = x, y, z, t, as complex [4, 4, 4] (from the C oracle)."""
+    g = np.zeros((4, 4, 4), dtype=np.complex128)
+    lib().orc_gammas(_dp(g))
+    return g
+
+
+# --- site-local algebra -----------------------------------------------------
+
+I2 = np.eye(2, dtype=np.complex128)
+GAMMA5 = np.block([[np.zeros((2, 2)), I2], [I2, np.zeros((2, 2))]]).astype(np.complex128)
+TAU1 = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+TAU3 = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+PLUS, MINUS, NDEG = 1, -1, 2
+
+
+@dataclass
+class Params:
+    """Operator parameters.  dims = (Lx, Ly, Lz, Lt); flavor in {PLUS, MINUS, NDEG}."""
+    dims: tuple
+    kappa: float
+    mu: float
+    eps: float = 0.0
+    flavor: int = PLUS
+    tsign: float = -1.0   # -1: antiperiodic in t
+
+    @property
+    def nf(self) -> int:
+        return 2 if self.flavor == NDEG else 1
+
+    @property
+    def a(self) -> float:
+        return 2.0 * self.kappa * self.mu
+
+    @property
+    def b(self) -> float:
+        return 2.0 * self.kappa * self.eps if self.flavor == NDEG else 0.0
+
+
+def twist_matrix(p: Params, inverse: bool = False, dagger: bool = False) -> np.ndarray:
+    """R or R^-1 (optionally daggered) as a (4 nf) x (4 nf) matrix on (flavour, spin)."""
+    if p.nf == 1:
+        s = 1.0 if p.flavor == PLUS else -1.0
+        if not inverse:
+            m = np.eye(4) + 1j * s * p.a * GAMMA5
+        else:
+            m = (np.eye(4) - 1j * s * p.a * GAMMA5) / (1.0 + p.a ** 2)
+    else:
+        if not inverse:
+            m = np.eye(8) + 1j * p.a * np.kron(TAU3, GAMMA5) + p.b * np.kron(TAU1, np.eye(4))
+        else:
+            d = 1.0 + p.a ** 2 - p.b ** 2
+            m = (np.eye(8) - 1j * p.a * np.kron(TAU3, GAMMA5) - p.b * np.kron(TAU1, np.eye(4))) / d
+    m = m.astype(np.complex128)
+    return m.conj().T.copy() if dagger else m
+
+
+def _site_apply(m: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    nf = psi.shape[-3]
+    sh = psi.shape
+    v = psi.reshape(sh[:-3] + (nf * 4, 3))
+    return np.einsum("ij,...jc->...ic", m, v).reshape(sh)
+
+
+def parity_mask(dims, parity: int) -> np.ndarray:
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx),
+                             indexing="ij")
+    return ((x + y + z + t) & 1) == parity
+
+
+def project(psi: np.ndarray, dims, parity: int) -> np.ndarray:
+    """Zero the sites of the other parity (psi canonical, optionally with a rhs axis)."""
+    m = parity_mask(dims, parity)[..., None, None, None]
+    return psi * m
+
+
+def twist(p: Params, psi: np.ndarray, inverse=False, dagger=False, parity: int = -1):
+    """R psi, R^-1 psi, R^+ psi or R^-+ psi on every site (parity -1) or one parity."""
+    out = _site_apply(twist_matrix(p, inverse, dagger), psi)
+    return out if parity < 0 else project(out, p.dims, parity)
+
+
+def hop(p: Params, U: np.ndarray, psi: np.ndarray, out_parity: int = -1, dagger=False):
+    """Wilson hop D psi (or D^+ psi) through the C loop; see tm_oracle.c."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    nrhs = 1 if psi.ndim == 7 else psi.shape[0]
+    assert psi.shape[-3] == p.nf
+    out = np.empty_like(psi)
+    dims = (ctypes.c_int * 4)(*p.dims)
+    lib().orc_hop(_dp(out), _dp(psi), _dp(U), dims, p.nf, nrhs, int(bool(dagger)),
+                  float(p.tsign), int(out_parity))
+    return out
+
+
+# --- full and preconditioned operators ---------------------------------------
+
+EVEN, ODD = 0, 1
+
+
+def full_M(p: Params, U, psi, dagger=False):
+    """M psi = R psi - kappa D psi (Eq. 2.1 times 2 kappa); M^+ = R^+ - kappa D^+."""
+    return twist(p, psi, dagger=dagger) - p.kappa * hop(p, U, psi, dagger=dagger)
+
+
+def mat_pc(p: Params, U, x_e, pc: str = "asym", dagger=False):
+    """Preconditioned even-even operator of Eq. (2.2) (asym) or Eq. (2.3) (sym)."""
+    k2 = p.kappa ** 2
+    if pc == "asym":
+        if not dagger:
+            t = twist(p, hop(p, U, x_e, ODD), inverse=True, parity=ODD)
+            return twist(p, x_e, parity=EVEN) - k2 * hop(p, U, t, EVEN)
+        # (R_ee - k^2 D_eo R_oo^-1 D_oe)^+ = R_ee^+ - k^2 (D_oe)^+ R_oo^-+ (D_eo)^+
+        t = twist(p, hop(p, U, x_e, ODD, dagger=True), inverse=True, dagger=True, parity=ODD)
+        return twist(p, x_e, dagger=True, parity=EVEN) - k2 * hop(p, U, t, EVEN, dagger=True)
+    if pc == "sym":
+        if not dagger:
+            t = twist(p, hop(p, U, x_e, ODD), inverse=True, parity=ODD)
+            return x_e - k2 * twist(p, hop(p, U, t, EVEN), inverse=True, parity=EVEN)
+        # (1 - k^2 R_ee^-1 D_eo R_oo^-1 D_oe)^+ = 1 - k^2 (D_oe)^+ R_oo^-+ (D_eo)^+ R_ee^-+
+        y = twist(p, x_e, inverse=True, dagger=True, parity=EVEN)
+        t = twist(p, hop(p, U, y, ODD, dagger=True), inverse=True, dagger=True, parity=ODD)
+        return x_e - k2 * hop(p, U, t, EVEN, dagger=True)
+    raise ValueError(pc)
+
+
+def normal_op(p: Params, U, x_e, pc="asym"):
+    return mat_pc(p, U, mat_pc(p, U, x_e, pc), pc, dagger=True)
+
+
+def prepare(p: Params, U, b, pc="asym"):
+    """Even right-hand side of the Schur system from a full source b."""
+    b_e = project(b, p.dims, EVEN)
+    b_o = project(b, p.dims, ODD)
+    rhs = b_e + p.kappa * hop(p, U, twist(p, b_o, inverse=True, parity=ODD), EVEN)
+    if pc == "sym":
+        rhs = twist(p, rhs, inverse=True, parity=EVEN)
+    return rhs
+
+
+def reconstruct(p: Params, U, x_e, b):
+    """Odd half of the solution: R_oo^-1 (b_o + kappa D_oe x_e)."""
+    b_o = project(b, p.dims, ODD)
+    return twist(p, b_o + p.kappa * hop(p, U, x_e, ODD), inverse=True, parity=ODD)
+
+
+def _dot(a, b):
+    return complex(np.vdot(a, b))
+
+
+def _nrm2(a):
+    return float(np.vdot(a, a).real)
+
+
+def cg(p: Params, U, b_e, pc="asym", tol=1e-10, maxiter=10000, x0=None):
+    """CG on M^+ M x = M^+ b in FP64 (normal equations, even sites).
+
+    Stops when the true residual |M^+ b - M^+ M x| <= tol |M^+ b|.  Returns
+    (x, info) with info = dict(iters, true_rel_res_normal, true_rel_res_pc).
+    """
+    c = mat_pc(p, U, b_e, pc, dagger=True)
+    x = np.zeros_like(b_e) if x0 is None else x0.copy()
+    r = c - normal_op(p, U, x, pc) if x0 is not None else c.copy()
+    cc = _nrm2(c)
+    pdir = r.copy()
+    rr = _nrm2(r)
+    it = 0
+    while it < maxiter:
+        if rr <= tol * tol * cc:
+            rtrue = c - normal_op(p, U, x, pc)
+            if _nrm2(rtrue) <= tol * tol * cc:
+                break
+            r = rtrue                       # restart from the true residual
+            rr = _nrm2(r)
+            pdir = r.copy()
+        mp = mat_pc(p, U, pdir, pc)
+        ap = mat_pc(p, U, mp, pc, dagger=True)
+        alpha = rr / _nrm2(mp)
+        x = x + alpha * pdir
+        r = r - alpha * ap
+        rr_new = _nrm2(r)
+        pdir = r + (rr_new / rr) * pdir
+        rr = rr_new
+        it += 1
+    rn = np.sqrt(_nrm2(c - normal_op(p, U, x, pc)) / cc)
+    rp = np.sqrt(_nrm2(b_e - mat_pc(p, U, x, pc)) / _nrm2(b_e))
+    return x, dict(iters=it, true_rel_res_normal=rn, true_rel_res_pc=rp)
+
+
+def solve(p: Params, U, b, pc="asym", tol=1e-12, maxiter=10000):
+    """Full solution of M psi = b by the Schur route: prepare, CG, reconstruct."""
+    rhs = prepare(p, U, b, pc)
+    x_e, info = cg(p, U, rhs, pc, tol, maxiter)
+    return x_e + reconstruct(p, U, x_e, b), info
