@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: twisted-mass Dslash Gflop/s + HBM GB/s on one MI355X, and mixed vs
+FP64 CG time to a 1e-10 residual.
+
+Timed step = one application of the asymmetric even-odd preconditioned operator
+(Eq. 2.2, the operator Table 1 of the paper measures): two fused hop kernels,
+FP32 storage and arithmetic, 12-real links, degenerate flavour, 24^3 x 48
+lattice (kappa = 0.1615, mu = 0.004, near-unit SU(3) links), inputs resident in
+HBM.  Flops per even site: 2808 (1320 per hop, twist and xpay as counted in
+the design notes); algorithmic bytes per even site: 16 L + 5 S.
+
+Also reported (not timed in the K steps): per-kernel durations from HIP events
+with the roofline of the dominant kernel, the FP64 CPU oracle on the host as a
+baseline, and the 32^3 x 64 non-degenerate doublet CG comparison (FP64 CG vs
+mixed precision with FP64 reliable updates) to a 1e-10 true residual.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tm Dslash Gflop/s + HBM GB/s; mixed vs FP64 CG time to 1e-10 residual"
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_SITE = {"deg_asym": 2808, "deg_sym": 2832, "nd": 5808}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def site_bytes(L, S):
+    """(K1, K2) algorithmic bytes per even site: K1 = 8L + 2S, K2 = 8L + 3S."""
+    return 8 * L + 2 * S, 8 * L + 3 * S
+
+
+def time_launches(torch, fn, reps):
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3   # seconds per launch
+
+
+def cpu_baseline(U, b_e, dims, vh, budget_s=15.0):
+    """The FP64 oracle's asymmetric operator apply on this host (C loop + NumPy)."""
+    from oracle import oracle as O
+    op = O.Params(dims, 0.1615, 0.004, 0.0, O.PLUS)
+    t0 = time.perf_counter()
+    O.mat_pc(op, U, b_e, "asym")
+    t1 = time.perf_counter() - t0
+    n = max(1, min(8, int(budget_s / max(t1, 1e-3))))
+    ts = [t1]
+    for _ in range(n - 1):
+        t0 = time.perf_counter()
+        O.mat_pc(op, U, b_e, "asym")
+        ts.append(time.perf_counter() - t0)
+    t = statistics.median(ts)
+    return {"value": round(FLOPS_PER_SITE["deg_asym"] * vh / t / 1e9, 3), "unit": "Gflop/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{len(ts)} FP64 applies of the asymmetric preconditioned operator at "
+                      f"{'x'.join(map(str, dims))} (median {t:.2f} s each)"}
+
+
+def cg_comparison(torch, api, inputs, reps=2):
+    """32^3 x 64 doublet, mu = 0.15, eps = 0.19, kappa = 0.1615: FP64 CG vs mixed CG."""
+    dims = (32, 32, 32, 64)
+    p = api.make_params(dims, 0.1615, 0.15, 0.19, api.NDEG)
+    log("cg: generating 32^3x64 links")
+    U = inputs.gauge_field(dims, "near_unit", 1003)
+    Ut = torch.from_numpy(U).cuda()
+    del U
+    ctx = api.Context()
+    g = api.Gauge(ctx, Ut, p, recon=12, precs=(api.FP64, api.FP32, api.FP16, api.BF16))
+    del Ut
+    b = inputs.gaussian_spinor(dims, 2, 2003)
+    tb = api.tm_spinor_pack(ctx, b[None], p, api.FP64, 0)
+    del b
+    out = {}
+    for name, inner in (("fp64", api.FP64), ("mixed_fp16", api.FP16), ("mixed_bf16", api.BF16),
+                        ("mixed_fp32", api.FP32)):
+        secs, res = [], None
+        for _ in range(reps):
+            x = api.new_field(p, api.FP64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = api.tm_cg(ctx, x, tb, g, pc=api.ASYM, tol=1e-10, maxiter=20000, inner=inner)[0]
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+        out[name] = {"seconds": round(statistics.median(secs), 4), "iters": res["iters"],
+                     "reliable_updates": res["reliable_updates"],
+                     "true_rel_res_normal": res["true_rel_res_normal"],
+                     "true_rel_res_pc": res["true_rel_res_pc"], "status": res["status"]}
+        log(f"cg {name}: {out[name]}")
+    g.close()
+    ctx.close()
+    out["speedup_fp16_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_fp16"]["seconds"], 3)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the lattice would be split in t with halo exchange; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1311_4462_amd import api, inputs
+
+    torch.cuda.set_device(0)
+    dims = (24, 24, 24, 48)
+    vh = int(np.prod(dims)) // 2
+    p = api.make_params(dims, 0.1615, 0.004, 0.0, api.PLUS)
+    log("bench: generating 24^3x48 links")
+    U = inputs.gauge_field(dims, "near_unit", 1002)
+    ctx = api.Context()
+    g = api.Gauge(ctx, torch.from_numpy(U).cuda(), p, recon=12, precs=(api.FP64, api.FP32))
+    b = inputs.gaussian_spinor(dims, 1, 2002)
+    from oracle import oracle as O  # only for the even projection of the CPU-baseline input
+    b_e = O.project(b, dims, 0) if not a.no_cpu_baseline else None
+    x = api.tm_spinor_pack(ctx, b[None], p, api.FP32, 0)
+    y = api.new_field(p, api.FP32)
+
+    def step():
+        api.tm_mat_pc(ctx, y, x, g, api.FP32, api.ASYM, 0)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    flops = FLOPS_PER_SITE["deg_asym"] * vh
+    value = flops / dt / 1e9
+
+    # per-kernel durations (HIP events on the stream the kernels run on)
+    L, S = 48, 96
+    b1, b2 = site_bytes(L, S)
+    tmp = api.new_field(p, api.FP32, 1)
+    kappa2 = -p.kappa ** 2
+    t_k1 = time_launches(torch, lambda: api.tm_dslash(ctx, tmp, x, g, api.FP32, 1, 0, 0,
+                                                      api.EPI_TWINV, None, 0.0), a.kernel_reps)
+    t_k2 = time_launches(torch, lambda: api.tm_dslash(ctx, y, tmp, g, api.FP32, 0, 0, 0,
+                                                      api.EPI_RX_PLUS_KD, x, kappa2), a.kernel_reps)
+    ach = b2 * vh / t_k2 / 1e9
+    mat_bytes = (b1 + b2) * vh
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "hop_kernel<FP32, 1 flavour, 1 rhs, 12-real links> with epilogue R x + k D",
+                "bytes_per_launch": b2 * vh, "us_per_launch": round(t_k2 * 1e6, 2)}
+    extra = {
+        "hbm_gbs_mat_pc": round(mat_bytes / dt / 1e9, 1),
+        "hbm_frac_mat_pc": round(mat_bytes / dt / 1e9 / PEAK_HBM_GBS, 4),
+        "kernel_us": {"hop_twinv": round(t_k1 * 1e6, 2), "hop_rx_plus_kd": round(t_k2 * 1e6, 2)},
+        "kernel_gbs": {"hop_twinv": round(b1 * vh / t_k1 / 1e9, 1),
+                       "hop_rx_plus_kd": round(ach, 1)},
+    }
+    log(f"mat_pc fp32: {dt * 1e6:.1f} us/apply, {value:.1f} Gflop/s, "
+        f"{extra['hbm_gbs_mat_pc']} GB/s; kernels {extra['kernel_us']}")
+
+    # FP64 operator on the same lattice (context figure)
+    x64 = api.tm_spinor_pack(ctx, b[None], p, api.FP64, 0)
+    y64 = api.new_field(p, api.FP64)
+    t64 = time_launches(torch, lambda: api.tm_mat_pc(ctx, y64, x64, g, api.FP64, api.ASYM, 0),
+                        a.kernel_reps)
+    extra["mat_pc_fp64"] = {"us": round(t64 * 1e6, 2), "gflops": round(flops / t64 / 1e9, 1),
+                            "gbs": round((16 * 96 + 5 * 192) * vh / t64 / 1e9, 1)}
+    del x64, y64
+    g.close()
+    ctx.close()
+    del U
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("cpu baseline: oracle applies")
+        Uc = inputs.gauge_field(dims, "near_unit", 1002)
+        cpu = cpu_baseline(Uc, b_e, dims, vh)
+        del Uc
+    if not a.no_cg:
+        extra["cg_32x32x32x64_nd"] = cg_comparison(torch, api, inputs)
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gflop/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(dt * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (near-unit random SU(3) links, Gaussian source)",
+        "config": {"workload": "tm_mat_pc asymmetric, degenerate, 24^3x48, FP32, 12-real links",
+                   "lattice": "24x24x24x48", "kappa": 0.1615, "mu": 0.004, "recon": 12,
+                   "parallelism": "1 GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * tm.h - C ABI of an MI355X-native library for the even-odd preconditioned
+ * Wilson twisted-mass Dirac operator (Strelchenko, Alexandrou, Koutsou,
+ * Vaquero, "Implementation of the twisted mass fermion operator in the QUDA
+ * library", LATTICE 2013, arXiv:1311.4462).
+ *
+ * Operator conventions (the paper leaves these open; every entry point follows
+ * them):
+ *   - Lattice extents dims = {Lx, Ly, Lz, Lt}, all even and >= 2.  Site
+ *     lex = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) & 1, even = 0;
+ *     checkerboard index cb = lex >> 1.
+ *   - Gamma matrices of the non-relativistic basis of Sec. 2, in 2x2 blocks
+ *     g_k = [[0, i s_k], [-i s_k, 0]], g_4 = diag(1, 1, -1, -1),
+ *     g5 = g1 g2 g3 g4 = [[0, 1], [1, 0]].
+ *   - Hop (Wilson term of Eq. 2.1, r = 1):
+ *       (D psi)(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu),
+ *     periodic in x, y, z; if t_antiperiodic, hops across t = Lt-1 <-> 0 get -1.
+ *     D^+ swaps the two projectors.
+ *   - M = R - kappa D (Eq. 2.1 times 2 kappa), R = 1 + i a g5 t3 + b t1 with
+ *     a = 2 kappa mu, b = 2 kappa epsilon; one flavour: R = 1 +- i a g5
+ *     (TM_TWIST_PLUS / TM_TWIST_MINUS, Sec. 2.2).  Flavour 0 has t3 = +1.
+ *     R^-1 = (1 - i a g5 t3 - b t1) / (1 + a^2 - b^2); R^+ = R(-mu, eps).
+ *   - Preconditioned even-even operators: asym = R_ee - kappa^2 D_eo R_oo^-1 D_oe
+ *     (Eq. 2.2), sym = 1 - kappa^2 R_ee^-1 D_eo R_oo^-1 D_oe (Eq. 2.3).
+ *
+ * Native field layouts (device memory, owned by the caller):
+ *   spinor, one parity, nrhs right-hand sides, nf flavours (1, or 2 for the
+ *   doublet): chunks [rhs][flavour][chunk][cb], each chunk holding
+ *   consecutive (spin, colour) complex numbers k = 3*spin + colour:
+ *       TM_FP64: 16-byte chunks of 1 complex  (12 chunks per site)
+ *       TM_FP32: 16-byte chunks of 2 complex  (6 chunks)
+ *       TM_FP16 / TM_BF16: 8-byte chunks of 2 complex (6 chunks), followed
+ *       (at a 256-byte aligned offset) by a float scale per [rhs][flavour][cb];
+ *       stored value = true value / scale, scale = max |real component| of
+ *       the site's 24 reals for that flavour.
+ *   Spin components 0, 1 (the "upper" pair) occupy the first half of the
+ *   chunks, so a time hop reads only half of a neighbour.
+ *   Canonical (host-side exchange) layout, complex128, full lattice:
+ *       spinor [nrhs][lex][nf][4][3], links [mu][lex][3][3] (row-major).
+ *
+ * Errors: every call returns TM_OK (0), an error (< 0) or the warning
+ * TM_NOT_CONVERGED (> 0).  Nothing aborts and no exception crosses the ABI.
+ * Arguments are validated before any device work; tm_last_error() returns a
+ * message for the last failing call on a context.  All device work is
+ * enqueued on the context's stream and is asynchronous unless stated.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TM_OK = 0,
+    TM_NOT_CONVERGED = 1,
+    TM_ERR_ARG = -1,       /* null pointer, bad enum, size mismatch           */
+    TM_ERR_DIMS = -2,      /* an extent is odd or < 2                         */
+    TM_ERR_PARITY = -3,    /* parity not 0 / 1                                */
+    TM_ERR_PREC = -4,      /* precision not built for this gauge / operation  */
+    TM_ERR_SINGULAR = -5,  /* |1 + a^2 - b^2| < 1e-12: R has no inverse       */
+    TM_ERR_NAN = -6,       /* non-finite residual or norm                      */
+    TM_ERR_HIP = -7,       /* HIP runtime error (text in tm_last_error)       */
+    TM_ERR_NOMEM = -8,     /* device allocation failed                        */
+    TM_ERR_LIMIT = -9      /* size beyond a documented limit                  */
+};
+
+typedef enum { TM_FP64 = 0, TM_FP32 = 1, TM_FP16 = 2, TM_BF16 = 3 } tm_prec;
+typedef enum { TM_TWIST_PLUS = 1, TM_TWIST_MINUS = -1, TM_TWIST_NDEG = 2 } tm_flavor;
+typedef enum { TM_PC_ASYM = 0, TM_PC_SYM = 1 } tm_pc;
+
+/* Epilogue of tm_dslash, with A = D in (or D^+ in), x the optional field of the
+ * output parity and R, R^-1 daggered when dagger = 1:                          */
+typedef enum {
+    TM_EPI_NONE = 0,              /* out = A                    */
+    TM_EPI_TWINV = 1,             /* out = R^-1 A               */
+    TM_EPI_RX_PLUS_KD = 2,        /* out = R x + k A            */
+    TM_EPI_X_PLUS_K_TWINV_D = 3,  /* out = x + k R^-1 A         */
+    TM_EPI_TWINV_X_PLUS_KD = 4,   /* out = R^-1 (x + k A)       */
+    TM_EPI_X_PLUS_KD = 5          /* out = x + k A              */
+} tm_epilogue;
+
+typedef struct {
+    int dims[4];          /* Lx, Ly, Lz, Lt: even, >= 2                         */
+    double kappa;         /* hopping parameter                                  */
+    double mu;            /* bare twisted mass of Eq. (2.1) (lattice units)      */
+    double epsilon;       /* bare flavour splitting of Eq. (2.1); doublet only   */
+    int flavor;           /* tm_flavor                                          */
+    int t_antiperiodic;   /* 1: antiperiodic in t, 0: periodic                  */
+} tm_params;
+
+typedef struct {
+    int pc;               /* tm_pc                                              */
+    double tol;           /* stop when |M^+b - M^+M x| <= tol |M^+b| (FP64)     */
+    int maxiter;          /* iteration cap (inner iterations for mixed)         */
+    int outer;            /* precision of x and b: TM_FP64                      */
+    int inner;            /* TM_FP64 (plain CG) or TM_FP32 / FP16 / BF16 (mixed) */
+    double delta;         /* reliable-update threshold (mixed), 0 -> 0.1        */
+    int use_x0;           /* 1: x holds the initial guess                       */
+    int nrhs;             /* right-hand sides solved together (>= 1)            */
+    int graph_iters;      /* > 0: capture this many iterations in a hipGraph    */
+    int check_every;      /* host convergence check period (0 -> 1)             */
+} tm_cg_params;
+
+typedef struct {
+    int iters;                    /* CG iterations performed                     */
+    int reliable_updates;         /* FP64 residual replacements (mixed)          */
+    double true_rel_res_normal;   /* |M^+b - M^+M x| / |M^+b|, FP64, recomputed  */
+    double true_rel_res_pc;       /* |b - M x| / |b|, FP64                       */
+    double seconds;               /* wall time of the solve (host clock)         */
+} tm_cg_result;
+
+typedef struct tm_ctx tm_ctx;
+typedef struct tm_gauge tm_gauge;
+
+/* Context: binds a HIP stream (NULL = the null stream) and owns workspace.
+ * Create/destroy synchronise the stream.                                      */
+int tm_ctx_create(tm_ctx **ctx, void *hip_stream);
+int tm_ctx_destroy(tm_ctx *ctx);
+int tm_ctx_set_stream(tm_ctx *ctx, void *hip_stream);
+const char *tm_error_string(int code);
+const char *tm_last_error(tm_ctx *ctx);
+
+/* Gauge field + operator parameters (the Dirac operator object, Sec. 2.1).
+ * links_dev: complex128 canonical links [4][V][3][3] on the device (read only
+ * during the call).  recon: 18 (full links) or 12 (rows 0 and 1 stored, row 2
+ * rebuilt as conj(row0 x row1), Sec. 3).  prec_mask: bit (1 << tm_prec) for
+ * every precision to build.  Validates dims (TM_ERR_DIMS) and the twist
+ * (TM_ERR_SINGULAR).  Synchronises the stream.                                */
+int tm_gauge_create(tm_ctx *ctx, tm_gauge **g, const void *links_dev, const tm_params *p,
+                    int recon, unsigned prec_mask);
+int tm_gauge_destroy(tm_gauge *g);
+/* Device bytes held by the packed links of one precision (0 if not built).    */
+size_t tm_gauge_bytes(const tm_gauge *g, tm_prec prec);
+
+/* Bytes of one parity of a native spinor field (all rhs, flavours, scales).   */
+size_t tm_spinor_bytes(const tm_params *p, tm_prec prec, int nrhs);
+
+/* Canonical complex128 full-lattice field [nrhs][V][nf][4][3] (device) <->
+ * native field of one parity.  Unpack writes only the sites of that parity.  */
+int tm_spinor_pack(tm_ctx *ctx, void *dst_native, const void *src_canonical,
+                   const tm_params *p, tm_prec prec, int parity, int nrhs);
+int tm_spinor_unpack(tm_ctx *ctx, void *dst_canonical, const void *src_native,
+                     const tm_params *p, tm_prec prec, int parity, int nrhs);
+
+/* Fused hop (Sec. 2.1, "fused kernels"): out (parity out_parity) = epilogue of
+ * D in or D^+ in (in has the other parity).  twist_on_load = 1 applies R^-1
+ * (R^-+ if dagger) to every neighbour before the hop, i.e. A = D R^-1 in.
+ * x may be NULL for TM_EPI_NONE / TM_EPI_TWINV.  All fields share prec.       */
+int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
+              int out_parity, int dagger, int twist_on_load, tm_epilogue epi,
+              const void *x, double k, int nrhs);
+
+/* Preconditioned operator of Eq. (2.2) (TM_PC_ASYM) or Eq. (2.3) (TM_PC_SYM),
+ * or its dagger, on even fields: two fused hop kernels with an odd temporary
+ * held by the context.  out_e and in_e must not alias.                        */
+int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, tm_prec prec,
+              tm_pc pc, int dagger, int nrhs);
+
+/* out = R^-1 in (R^-+ in if dagger) on one parity (the twist is site-local and
+ * uniform, so parity only selects the field size); inverse = 0 gives R, R^+.  */
+int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
+             int parity, int dagger, int inverse, int nrhs);
+int tm_twist_inv(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
+                 int parity, int dagger, int nrhs);
+
+/* Right-hand side of Eq. (2.2) / (2.3): bhat_e = b_e + kappa D_eo R_oo^-1 b_o
+ * (asym), R_ee^-1 times that (sym).  (The printed equations omit the kappa
+ * that the kappa^2 of their left-hand side requires.)                         */
+int tm_prepare(tm_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o, const tm_gauge *g,
+               tm_prec prec, tm_pc pc, int nrhs);
+
+/* Odd half of the solution (Eq. 2.4 read for the unpreconditioned even
+ * solution): x_o = R_oo^-1 (b_o + kappa D_oe x_e).                            */
+int tm_reconstruct_odd(tm_ctx *ctx, void *x_o, const void *x_e, const void *b_o,
+                       const tm_gauge *g, tm_prec prec, int nrhs);
+
+/* CG on the normal equations M^+ M x = M^+ b of the preconditioned operator
+ * (NORMOP_PC solve, Sec. 2.2).  x_e, b_e: native even fields in precision
+ * par->outer (TM_FP64), par->nrhs right-hand sides.  inner = TM_FP64: plain
+ * FP64 CG; inner = FP32 / FP16 / BF16: mixed precision with reliable updates
+ * (low-precision iterations; FP64 true residual, reductions and solution
+ * accumulation).  res: array of par->nrhs results.  Synchronous.  Returns
+ * TM_NOT_CONVERGED if some rhs missed tol within maxiter (x, res filled).     */
+int tm_cg(tm_ctx *ctx, void *x_e, const void *b_e, const tm_gauge *g, const tm_cg_params *par,
+          tm_cg_result *res);
+
+/* One CG over several independent problems of uneven lattice size (each its
+ * own gauge / operator, nrhs[i] sources), every stage of an iteration being
+ * one kernel launch over all problems.  At most 8 problems.                   */
+int tm_cg_batched(tm_ctx *ctx, int nproblems, const tm_gauge *const *g, void *const *x_e,
+                  const void *const *b_e, const int *nrhs, const tm_cg_params *par,
+                  tm_cg_result *res);
+
+/* Native-field BLAS used by the solvers, exposed for tests and clients.
+ * Results are written to host memory (synchronous).                           */
+int tm_norm2(tm_ctx *ctx, double *out_host, const void *x, const tm_params *p, tm_prec prec,
+             int nrhs);
+int tm_dot(tm_ctx *ctx, double *out_host /* 2*nrhs: re, im */, const void *x, const void *y,
+           const tm_params *p, tm_prec prec, int nrhs);
+/* dst = src converted between precisions (same parity, nrhs).                 */
+int tm_convert(tm_ctx *ctx, void *dst, tm_prec dst_prec, const void *src, tm_prec src_prec,
+               const tm_params *p, int nrhs);
+
+/* Gauge force for S = phi^+ (M^+ M)^-1 phi with M the asymmetric (or
+ * symmetric) preconditioned operator and X = (M^+ M)^-1 phi given (even,
+ * native, precision prec).  F_dev: complex [4][V][3][3] canonical, FP32
+ * (force_prec = TM_FP32) or FP64, the traceless anti-Hermitian dS/dU in the
+ * convention dS/dw^a = -2 tr(F T^a) for U -> exp(w^a T^a) U, T^a = i lambda_a/2;
+ * scaled by coeff and added to F_dev if accumulate.  G_dev (nullable, same
+ * type and shape): the unconstrained complex gradient with dS = Re tr(G^+ dU). */
+int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm_gauge *g,
+             tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev);
+
+/* Autotuner: 1 enables timing-based choice of block size per kernel and shape
+ * (cached per context; persisted to $TM_TUNE_CACHE if set), 0 disables.       */
+int tm_set_tuning(tm_ctx *ctx, int enable);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TM_H */

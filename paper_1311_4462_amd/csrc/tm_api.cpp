@@ -1,0 +1,1191 @@
+// Host runtime behind include/tm.h: contexts, packed gauge fields, argument
+// validation, operator composition (Eqs. 2.2 - 2.4) and the CG drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "tm_fields.h"
+
+using namespace twm;
+
+// ------------------------------------------------------------------ objects
+
+struct Buf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct tm_ctx {
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;   // used for graph capture when stream is the null stream
+    int device = 0;
+    std::string last_error;
+    std::map<std::string, Buf> ws;
+    double *host_scratch = nullptr;   // pinned, for reduction results
+    size_t host_scratch_bytes = 0;
+    int tuning = 0;
+    std::map<std::string, int> tuned;  // kernel key -> block size
+    int xcd_remap = 1;
+};
+
+struct tm_gauge {
+    tm_ctx *ctx = nullptr;
+    tm_params p{};
+    int recon = 12;
+    int nf = 1;
+    uint32_t vh = 0;
+    void *links[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+};
+
+namespace {
+
+int fail(tm_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+    }
+    return code;
+}
+
+#define TM_HIP(ctx, call)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, TM_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+#define TM_TRY(expr)          \
+    do {                      \
+        int rc_ = (expr);     \
+        if (rc_ < 0) return rc_; \
+    } while (0)
+
+bool valid_prec(int p) { return p >= TM_FP64 && p <= TM_BF16; }
+
+int check_params(tm_ctx *ctx, const tm_params *p)
+{
+    if (!p) return fail(ctx, TM_ERR_ARG, "null params");
+    for (int d = 0; d < 4; d++)
+        if (p->dims[d] < 2 || (p->dims[d] & 1))
+            return fail(ctx, TM_ERR_DIMS, "extent %d of dimension %d is not even and >= 2",
+                        p->dims[d], d);
+    const double V = (double)p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
+    if (V / 2 > 2.0e8) return fail(ctx, TM_ERR_LIMIT, "lattice too large for one device");
+    if (p->flavor != TM_TWIST_PLUS && p->flavor != TM_TWIST_MINUS && p->flavor != TM_TWIST_NDEG)
+        return fail(ctx, TM_ERR_ARG, "bad twist flavor %d", p->flavor);
+    if (!std::isfinite(p->kappa) || !std::isfinite(p->mu) || !std::isfinite(p->epsilon))
+        return fail(ctx, TM_ERR_ARG, "non-finite operator parameter");
+    const double a = 2 * p->kappa * p->mu;
+    const double b = p->flavor == TM_TWIST_NDEG ? 2 * p->kappa * p->epsilon : 0.0;
+    if (std::fabs(1 + a * a - b * b) < 1e-12)
+        return fail(ctx, TM_ERR_SINGULAR, "twist R is singular: 1 + a^2 - b^2 = %g", 1 + a * a - b * b);
+    return TM_OK;
+}
+
+int nflav(const tm_params &p) { return p.flavor == TM_TWIST_NDEG ? 2 : 1; }
+uint32_t half_volume(const tm_params &p)
+{
+    return (uint32_t)((long)p.dims[0] * p.dims[1] * p.dims[2] * p.dims[3] / 2);
+}
+
+Twist make_twist(const tm_params &p, int dagger)
+{
+    const double a = 2 * p.kappa * p.mu;
+    Twist t;
+    if (p.flavor == TM_TWIST_NDEG) {
+        t.ta = dagger ? -a : a;
+        t.b = 2 * p.kappa * p.epsilon;
+    } else {
+        const double s = (p.flavor == TM_TWIST_PLUS) ? 1.0 : -1.0;
+        t.ta = dagger ? -s * a : s * a;
+        t.b = 0.0;
+    }
+    t.c = 1.0 / (1.0 + t.ta * t.ta - t.b * t.b);
+    return t;
+}
+
+SpinorPtr sptr(const void *p, int prec, uint32_t vh, int nf, int nrhs)
+{
+    SpinorPtr s;
+    s.data = const_cast<void *>(p);
+    s.scale = (prec == TM_FP16 || prec == TM_BF16)
+                  ? (float *)((char *)const_cast<void *>(p) + chunk_bytes(prec, vh, nf, nrhs))
+                  : nullptr;
+    return s;
+}
+
+void *workspace(tm_ctx *ctx, const std::string &name, size_t bytes, int *rc)
+{
+    Buf &b = ctx->ws[name];
+    if (b.bytes >= bytes && b.ptr) return b.ptr;
+    if (b.ptr) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+        b.ptr = nullptr;
+        *rc = fail(ctx, TM_ERR_NOMEM, "workspace %s: cannot allocate %zu bytes", name.c_str(), bytes);
+        return nullptr;
+    }
+    // counters must start at zero; everything else is written before use
+    (void)hipMemsetAsync(b.ptr, 0, bytes, ctx->stream);
+    b.bytes = bytes;
+    return b.ptr;
+}
+
+double *host_scratch(tm_ctx *ctx, size_t n, int *rc)
+{
+    const size_t bytes = n * sizeof(double);
+    if (ctx->host_scratch_bytes >= bytes) return ctx->host_scratch;
+    if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
+    ctx->host_scratch = nullptr;
+    ctx->host_scratch_bytes = 0;
+    if (hipHostMalloc((void **)&ctx->host_scratch, bytes, hipHostMallocDefault) != hipSuccess) {
+        *rc = fail(ctx, TM_ERR_NOMEM, "pinned host buffer of %zu bytes", bytes);
+        return nullptr;
+    }
+    ctx->host_scratch_bytes = bytes;
+    return ctx->host_scratch;
+}
+
+// Reduction slot i: a counter and a partial-sum buffer (stream ordered, so
+// consecutive launches can share one slot; a batched launch uses one per problem).
+struct RedSlot {
+    unsigned *counter;
+    double *partials;
+};
+
+int red_slot(tm_ctx *ctx, int i, size_t npartials, RedSlot *out)
+{
+    int rc = TM_OK;
+    char name[64];
+    snprintf(name, sizeof(name), "red_counter_%d", i);
+    out->counter = (unsigned *)workspace(ctx, name, 256, &rc);
+    if (!out->counter) return rc;
+    snprintf(name, sizeof(name), "red_partials_%d", i);
+    out->partials = (double *)workspace(ctx, name, std::max<size_t>(npartials, 64) * sizeof(double), &rc);
+    if (!out->partials) return rc;
+    return TM_OK;
+}
+
+// ------------------------------------------------------------------ hop launch
+
+struct HopCall {
+    const tm_gauge *g;
+    int prec;
+    int out_parity;
+    int dagger;
+    int twl;
+    int epi;
+    const void *in;
+    void *out;
+    const void *x;
+    double k;
+    int nrhs;
+    int fin;                 // FinOp for |out|^2 (FIN_NONE: no reduction)
+    CGScalars *cg;
+    double *red_out;
+};
+
+int choose_nr(int nf, int nrhs, int recon)
+{
+    if (nf == 1 && recon == 12 && nrhs % 4 == 0) return 4;
+    return 1;
+}
+
+int choose_bs(tm_ctx *ctx, int prec, int nf, int nr, int twl, int recon)
+{
+    if (twl || recon != 12) return 256;
+    char key[64];
+    snprintf(key, sizeof(key), "hop_p%d_f%d_r%d_c%d", prec, nf, nr, recon);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) return it->second;
+    return 256;
+}
+
+hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger, int twl, int recon,
+                        int bs, hipStream_t st)
+{
+    switch (prec) {
+    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, bs, st);
+    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, bs, st);
+    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, bs, st);
+    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, bs, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// One launch of the fused hop over up to kMaxProblems problems (same
+// precision, flavour count, recon, dagger, epilogue and rhs grouping).
+int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
+{
+    if (n < 1 || n > kMaxProblems) return fail(ctx, TM_ERR_LIMIT, "too many problems in a batch");
+    const tm_gauge *g0 = calls[0].g;
+    const int prec = calls[0].prec, nf = g0->nf, recon = g0->recon;
+    int nr = 1 << 30;
+    for (int i = 0; i < n; i++) nr = std::min(nr, choose_nr(nf, calls[i].nrhs, recon));
+    for (int i = 0; i < n; i++)
+        if (calls[i].nrhs % nr) nr = 1;
+    const int bs = choose_bs(ctx, prec, nf, nr, calls[0].twl, recon);
+
+    HopBatch B;
+    memset(&B, 0, sizeof(B));
+    B.nprob = n;
+    B.epi = calls[0].epi;
+    B.xcd_remap = ctx->xcd_remap;
+    int blocks = 0;
+    for (int i = 0; i < n; i++) {
+        const HopCall &c = calls[i];
+        const tm_gauge *g = c.g;
+        if (!g->links[prec][0]) return fail(ctx, TM_ERR_PREC, "gauge not built in precision %d", prec);
+        HopProblem &hp = B.p[i];
+        for (int d = 0; d < 4; d++) hp.X[d] = g->p.dims[d];
+        hp.vh = (int)g->vh;
+        hp.nrhs = c.nrhs;
+        hp.blk_start = blocks;
+        hp.nsb = (int)((g->vh + bs - 1) / bs);
+        hp.ngrp = c.nrhs / nr;
+        hp.out_parity = c.out_parity;
+        hp.tsign = g->p.t_antiperiodic ? -1.0 : 1.0;
+        hp.tw = make_twist(g->p, c.dagger);
+        hp.k = c.k;
+        hp.gauge[0] = g->links[prec][0];
+        hp.gauge[1] = g->links[prec][1];
+        hp.in = sptr(c.in, prec, g->vh, nf, c.nrhs);
+        hp.out = sptr(c.out, prec, g->vh, nf, c.nrhs);
+        hp.x = c.x ? sptr(c.x, prec, g->vh, nf, c.nrhs) : SpinorPtr{nullptr, nullptr};
+        hp.red.op = c.fin;
+        if (c.fin != FIN_NONE) {
+            RedSlot rs;
+            TM_TRY(red_slot(ctx, i, (size_t)hp.nsb * c.nrhs, &rs));
+            hp.red.partials = rs.partials;
+            hp.red.counter = rs.counter;
+            hp.red.cg = c.cg;
+            hp.red.out = c.red_out;
+        }
+        blocks += hp.nsb * hp.ngrp;
+    }
+    B.total_blocks = blocks;
+    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, calls[0].dagger, calls[0].twl, recon, bs, ctx->stream));
+    return TM_OK;
+}
+
+int hop1(tm_ctx *ctx, const HopCall &c) { return launch_hops(ctx, &c, 1); }
+
+// ------------------------------------------------------------------ BLAS launch
+
+struct BlasCall {
+    uint32_t vh;
+    int nrhs;
+    const void *v[4];
+    int fin;
+    CGScalars *cg;
+    double *red_out;
+};
+
+int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCall *calls, int n)
+{
+    if (n < 1 || n > kMaxProblems) return fail(ctx, TM_ERR_LIMIT, "too many problems in a batch");
+    BlasBatch B;
+    memset(&B, 0, sizeof(B));
+    B.nprob = n;
+    B.nf = nf;
+    int blocks = 0;
+    for (int i = 0; i < n; i++) {
+        const BlasCall &c = calls[i];
+        BlasProblem &bp = B.p[i];
+        bp.vh = c.vh;
+        bp.nrhs = c.nrhs;
+        bp.blk_start = blocks;
+        bp.nblk = (int)std::min<uint32_t>((c.vh + 255) / 256, 1024u);
+        // vector precisions per operation (see BlasOp)
+        int vp[4] = {pa, pa, pa, pa};
+        switch (op) {
+        case OP_CG_UPDATE: vp[1] = vp[2] = vp[3] = pb; break;
+        case OP_XPAY: vp[0] = vp[1] = pb; break;
+        case OP_RESIDUAL: vp[2] = vp[3] = pb; break;
+        case OP_CONVERT: vp[1] = pb; break;
+        case OP_ACCUM_ZERO: vp[1] = pb; break;
+        default: break;
+        }
+        for (int j = 0; j < 4; j++)
+            bp.v[j] = c.v[j] ? sptr(c.v[j], vp[j], c.vh, nf, c.nrhs) : SpinorPtr{nullptr, nullptr};
+        bp.red.op = c.fin;
+        if (c.fin != FIN_NONE) {
+            RedSlot rs;
+            TM_TRY(red_slot(ctx, i, (size_t)bp.nblk * c.nrhs * 2, &rs));
+            bp.red.partials = rs.partials;
+            bp.red.counter = rs.counter;
+            bp.red.cg = c.cg;
+            bp.red.out = c.red_out;
+        }
+        blocks += bp.nblk * c.nrhs;
+    }
+    B.total_blocks = blocks;
+    TM_HIP(ctx, launch_blas(op, pa, pb, B, ctx->stream));
+    return TM_OK;
+}
+
+int blas1(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCall &c)
+{
+    return launch_blas_batch(ctx, op, pa, pb, nf, &c, 1);
+}
+
+// ------------------------------------------------------------------ operators
+
+// Odd temporary of the preconditioned operator, one per problem slot and precision.
+void *odd_tmp(tm_ctx *ctx, int slot, const tm_gauge *g, int prec, int nrhs, int *rc)
+{
+    char name[64];
+    snprintf(name, sizeof(name), "odd_tmp_%d_%d", slot, prec);
+    return workspace(ctx, name, spinor_field_bytes(prec, g->vh, g->nf, nrhs), rc);
+}
+
+// The two fused kernels of the preconditioned operator (Sec. 2.1):
+//   asym:  t = R_oo^-1 D_oe x;   out = R_ee x - kappa^2 D_eo t
+//   sym:   t = R_oo^-1 D_oe x;   out = x - kappa^2 R_ee^-1 D_eo t
+//   asym^+: the same with D^+ and R^+ (twist of -mu)
+//   sym^+:  t = R_oo^-+ D^+_oe R_ee^-+ x (twist on load); out = x - kappa^2 D^+_eo t
+// Over n problems at once; `fin` reduces |out|^2 per rhs.
+int mat_pc_batch(tm_ctx *ctx, const tm_gauge *const *g, void *const *out, const void *const *in,
+                 const int *nrhs, int n, int prec, int pc, int dagger, int fin, CGScalars *const *cg)
+{
+    HopCall k1[kMaxProblems], k2[kMaxProblems];
+    for (int i = 0; i < n; i++) {
+        int rc = TM_OK;
+        void *tmp = odd_tmp(ctx, i, g[i], prec, nrhs[i], &rc);
+        if (!tmp) return rc;
+        const double k2c = -g[i]->p.kappa * g[i]->p.kappa;
+        k1[i] = HopCall{g[i], prec, 1, dagger, 0, TM_EPI_TWINV, in[i], tmp, nullptr, 0.0, nrhs[i],
+                        FIN_NONE, nullptr, nullptr};
+        k2[i] = HopCall{g[i], prec, 0, dagger, 0, TM_EPI_RX_PLUS_KD, tmp, out[i], in[i], k2c, nrhs[i],
+                        fin, cg ? cg[i] : nullptr, nullptr};
+        if (pc == TM_PC_SYM) {
+            if (!dagger) {
+                k2[i].epi = TM_EPI_X_PLUS_K_TWINV_D;
+            } else {
+                k1[i].twl = 1;
+                k2[i].epi = TM_EPI_X_PLUS_KD;
+            }
+        }
+    }
+    TM_TRY(launch_hops(ctx, k1, n));
+    TM_TRY(launch_hops(ctx, k2, n));
+    return TM_OK;
+}
+
+int check_gauge_prec(tm_ctx *ctx, const tm_gauge *g, int prec)
+{
+    if (!g) return fail(ctx, TM_ERR_ARG, "null gauge");
+    if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision %d", prec);
+    if (!g->links[prec][0]) return fail(ctx, TM_ERR_PREC, "gauge not built in precision %d", prec);
+    return TM_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char *tm_error_string(int code)
+{
+    switch (code) {
+    case TM_OK: return "ok";
+    case TM_NOT_CONVERGED: return "solver did not converge within maxiter";
+    case TM_ERR_ARG: return "invalid argument";
+    case TM_ERR_DIMS: return "lattice extents must be even and >= 2";
+    case TM_ERR_PARITY: return "parity must be 0 (even) or 1 (odd)";
+    case TM_ERR_PREC: return "precision not available";
+    case TM_ERR_SINGULAR: return "twist R is singular (1 + a^2 - b^2 = 0)";
+    case TM_ERR_NAN: return "non-finite value";
+    case TM_ERR_HIP: return "HIP runtime error";
+    case TM_ERR_NOMEM: return "out of device memory";
+    case TM_ERR_LIMIT: return "size beyond a library limit";
+    }
+    return "unknown error";
+}
+
+const char *tm_last_error(tm_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
+{
+    if (!ctx) return TM_ERR_ARG;
+    tm_ctx *c = new tm_ctx();
+    c->stream = (hipStream_t)hip_stream;
+    // Without a device the context still validates arguments (every check
+    // runs before the first HIP call); device work then fails with TM_ERR_HIP.
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    const char *e = getenv("TM_XCD_REMAP");
+    if (e) c->xcd_remap = atoi(e);
+    *ctx = c;
+    return TM_OK;
+}
+
+int tm_ctx_set_stream(tm_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return TM_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return TM_OK;
+}
+
+int tm_ctx_destroy(tm_ctx *ctx)
+{
+    if (!ctx) return TM_ERR_ARG;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->ws)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+    return TM_OK;
+}
+
+int tm_set_tuning(tm_ctx *ctx, int enable)
+{
+    if (!ctx) return TM_ERR_ARG;
+    ctx->tuning = enable ? 1 : 0;
+    return TM_OK;
+}
+
+int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const tm_params *p,
+                    int recon, unsigned prec_mask)
+{
+    if (!ctx) return TM_ERR_ARG;
+    if (!gout || !links_dev) return fail(ctx, TM_ERR_ARG, "null gauge output or links");
+    TM_TRY(check_params(ctx, p));
+    if (p->t_antiperiodic != 0 && p->t_antiperiodic != 1)
+        return fail(ctx, TM_ERR_ARG, "t_antiperiodic must be 0 or 1");
+    if (recon != 12 && recon != 18) return fail(ctx, TM_ERR_ARG, "recon must be 12 or 18");
+    if (prec_mask == 0 || (prec_mask & ~0xFu)) return fail(ctx, TM_ERR_PREC, "bad precision mask");
+    tm_gauge *g = new tm_gauge();
+    g->ctx = ctx;
+    g->p = *p;
+    g->recon = recon;
+    g->nf = nflav(*p);
+    g->vh = half_volume(*p);
+    for (int prec = 0; prec < 4; prec++) {
+        if (!(prec_mask & (1u << prec))) continue;
+        for (int par = 0; par < 2; par++) {
+            if (hipMalloc(&g->links[prec][par], gauge_parity_bytes(prec, recon, g->vh)) != hipSuccess) {
+                g->links[prec][par] = nullptr;
+                tm_gauge_destroy(g);
+                return fail(ctx, TM_ERR_NOMEM, "cannot allocate packed links");
+            }
+        }
+        hipError_t e = gauge_pack(prec, recon, g->links[prec][0], g->links[prec][1], links_dev,
+                                  p->dims, g->vh, ctx->stream);
+        if (e != hipSuccess) {
+            tm_gauge_destroy(g);
+            return fail(ctx, TM_ERR_HIP, "gauge pack: %s", hipGetErrorString(e));
+        }
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        tm_gauge_destroy(g);
+        return fail(ctx, TM_ERR_HIP, "gauge pack: %s", hipGetErrorString(e));
+    }
+    *gout = g;
+    return TM_OK;
+}
+
+int tm_gauge_destroy(tm_gauge *g)
+{
+    if (!g) return TM_ERR_ARG;
+    if (g->ctx) (void)hipStreamSynchronize(g->ctx->stream);
+    for (int prec = 0; prec < 4; prec++)
+        for (int par = 0; par < 2; par++)
+            if (g->links[prec][par]) (void)hipFree(g->links[prec][par]);
+    delete g;
+    return TM_OK;
+}
+
+size_t tm_gauge_bytes(const tm_gauge *g, tm_prec prec)
+{
+    if (!g || !valid_prec(prec) || !g->links[prec][0]) return 0;
+    return 2 * gauge_parity_bytes(prec, g->recon, g->vh);
+}
+
+size_t tm_spinor_bytes(const tm_params *p, tm_prec prec, int nrhs)
+{
+    if (!p || !valid_prec(prec) || nrhs < 1) return 0;
+    if (check_params(nullptr, p) != TM_OK) return 0;
+    return spinor_field_bytes(prec, half_volume(*p), nflav(*p), nrhs);
+}
+
+int tm_spinor_pack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, tm_prec prec,
+                   int parity, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_params(ctx, p));
+    if (!dst || !src) return fail(ctx, TM_ERR_ARG, "null field");
+    if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
+    if (parity != 0 && parity != 1) return fail(ctx, TM_ERR_PARITY, "bad parity %d", parity);
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    const uint32_t vh = half_volume(*p);
+    const int nf = nflav(*p);
+    TM_HIP(ctx, spinor_pack(prec, sptr(dst, prec, vh, nf, nrhs), src, p->dims, vh, parity, nf, nrhs,
+                            ctx->stream));
+    return TM_OK;
+}
+
+int tm_spinor_unpack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, tm_prec prec,
+                     int parity, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_params(ctx, p));
+    if (!dst || !src) return fail(ctx, TM_ERR_ARG, "null field");
+    if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
+    if (parity != 0 && parity != 1) return fail(ctx, TM_ERR_PARITY, "bad parity %d", parity);
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    const uint32_t vh = half_volume(*p);
+    const int nf = nflav(*p);
+    TM_HIP(ctx, spinor_unpack(prec, dst, sptr(src, prec, vh, nf, nrhs), p->dims, vh, parity, nf,
+                              nrhs, ctx->stream));
+    return TM_OK;
+}
+
+int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
+              int out_parity, int dagger, int twist_on_load, tm_epilogue epi, const void *x,
+              double k, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_gauge_prec(ctx, g, prec));
+    if (!out || !in) return fail(ctx, TM_ERR_ARG, "null field");
+    if (out == in) return fail(ctx, TM_ERR_ARG, "out and in must not alias");
+    if (out_parity != 0 && out_parity != 1) return fail(ctx, TM_ERR_PARITY, "bad parity");
+    if ((int)epi < TM_EPI_NONE || (int)epi > TM_EPI_X_PLUS_KD) return fail(ctx, TM_ERR_ARG, "bad epilogue");
+    if ((int)epi >= TM_EPI_RX_PLUS_KD && !x) return fail(ctx, TM_ERR_ARG, "epilogue needs x");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    if (!std::isfinite(k)) return fail(ctx, TM_ERR_ARG, "non-finite k");
+    HopCall c{g, prec, out_parity, dagger ? 1 : 0, twist_on_load ? 1 : 0, (int)epi, in, out, x, k,
+              nrhs, FIN_NONE, nullptr, nullptr};
+    return hop1(ctx, c);
+}
+
+int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, tm_prec prec,
+              tm_pc pc, int dagger, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_gauge_prec(ctx, g, prec));
+    if (!out_e || !in_e) return fail(ctx, TM_ERR_ARG, "null field");
+    if (out_e == in_e) return fail(ctx, TM_ERR_ARG, "out and in must not alias");
+    if (pc != TM_PC_ASYM && pc != TM_PC_SYM) return fail(ctx, TM_ERR_ARG, "bad pc type");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    return mat_pc_batch(ctx, &g, &out_e, &in_e, &nrhs, 1, prec, pc, dagger ? 1 : 0, FIN_NONE, nullptr);
+}
+
+int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec, int parity,
+             int dagger, int inverse, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_gauge_prec(ctx, g, prec));
+    if (!out || !in) return fail(ctx, TM_ERR_ARG, "null field");
+    if (parity != 0 && parity != 1) return fail(ctx, TM_ERR_PARITY, "bad parity");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    TM_HIP(ctx, twist_apply(prec, g->nf, sptr(out, prec, g->vh, g->nf, nrhs),
+                            sptr(in, prec, g->vh, g->nf, nrhs), g->vh, nrhs,
+                            make_twist(g->p, dagger ? 1 : 0), inverse ? 1 : 0, ctx->stream));
+    return TM_OK;
+}
+
+int tm_twist_inv(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec, int parity,
+                 int dagger, int nrhs)
+{
+    return tm_twist(ctx, out, in, g, prec, parity, dagger, 1, nrhs);
+}
+
+int tm_prepare(tm_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o, const tm_gauge *g,
+               tm_prec prec, tm_pc pc, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_gauge_prec(ctx, g, prec));
+    if (!bhat_e || !b_e || !b_o) return fail(ctx, TM_ERR_ARG, "null field");
+    if (bhat_e == b_o) return fail(ctx, TM_ERR_ARG, "bhat_e and b_o must not alias");
+    if (pc != TM_PC_ASYM && pc != TM_PC_SYM) return fail(ctx, TM_ERR_ARG, "bad pc type");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    HopCall c{g, prec, 0, 0, 1, pc == TM_PC_SYM ? TM_EPI_TWINV_X_PLUS_KD : TM_EPI_X_PLUS_KD, b_o,
+              bhat_e, b_e, g->p.kappa, nrhs, FIN_NONE, nullptr, nullptr};
+    return hop1(ctx, c);
+}
+
+int tm_reconstruct_odd(tm_ctx *ctx, void *x_o, const void *x_e, const void *b_o, const tm_gauge *g,
+                       tm_prec prec, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_gauge_prec(ctx, g, prec));
+    if (!x_o || !x_e || !b_o) return fail(ctx, TM_ERR_ARG, "null field");
+    if (x_o == x_e) return fail(ctx, TM_ERR_ARG, "x_o and x_e must not alias");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    HopCall c{g, prec, 1, 0, 0, TM_EPI_TWINV_X_PLUS_KD, x_e, x_o, b_o, g->p.kappa, nrhs, FIN_NONE,
+              nullptr, nullptr};
+    return hop1(ctx, c);
+}
+
+static int reduce_to_host(tm_ctx *ctx, int op, int prec, const tm_params *p, const void *x,
+                          const void *y, int nrhs, double *out_host, int nout)
+{
+    int rc = TM_OK;
+    double *dres = (double *)workspace(ctx, "red_result", (size_t)nout * sizeof(double), &rc);
+    if (!dres) return rc;
+    double *h = host_scratch(ctx, nout, &rc);
+    if (!h) return rc;
+    BlasCall c{half_volume(*p), nrhs, {x, y, nullptr, nullptr}, FIN_STORE, nullptr, dres};
+    TM_TRY(blas1(ctx, op, prec, prec, nflav(*p), c));
+    TM_HIP(ctx, hipMemcpyAsync(h, dres, nout * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    memcpy(out_host, h, nout * sizeof(double));
+    return TM_OK;
+}
+
+int tm_norm2(tm_ctx *ctx, double *out_host, const void *x, const tm_params *p, tm_prec prec, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_params(ctx, p));
+    if (!out_host || !x) return fail(ctx, TM_ERR_ARG, "null pointer");
+    if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    return reduce_to_host(ctx, OP_NORM2, prec, p, x, nullptr, nrhs, out_host, nrhs);
+}
+
+int tm_dot(tm_ctx *ctx, double *out_host, const void *x, const void *y, const tm_params *p,
+           tm_prec prec, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_params(ctx, p));
+    if (!out_host || !x || !y) return fail(ctx, TM_ERR_ARG, "null pointer");
+    if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    return reduce_to_host(ctx, OP_DOT, prec, p, x, y, nrhs, out_host, 2 * nrhs);
+}
+
+int tm_convert(tm_ctx *ctx, void *dst, tm_prec dst_prec, const void *src, tm_prec src_prec,
+               const tm_params *p, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_params(ctx, p));
+    if (!dst || !src) return fail(ctx, TM_ERR_ARG, "null field");
+    if (!valid_prec(dst_prec) || !valid_prec(src_prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    BlasCall c{half_volume(*p), nrhs, {src, dst, nullptr, nullptr}, FIN_NONE, nullptr, nullptr};
+    return blas1(ctx, OP_CONVERT, src_prec, dst_prec, nflav(*p), c);
+}
+
+// ------------------------------------------------------------------ CG
+
+namespace {
+
+struct CGProblem {
+    const tm_gauge *g;
+    int nrhs;
+    void *x;            // FP64 solution (user)
+    const void *b;      // FP64 rhs (user)
+    // FP64 work vectors
+    void *c, *y, *r64, *p64, *mp64, *ap64;
+    // low-precision work vectors (mixed)
+    void *rlo, *plo, *mplo, *aplo, *xlo;
+    CGScalars *cg;      // device [nrhs]
+    double *dres;       // device [2*nrhs] norms
+    double cc[64];      // |c|^2 per rhs (host)
+};
+
+int cg_setup_vectors(tm_ctx *ctx, CGProblem &pr, int slot, int inner)
+{
+    int rc = TM_OK;
+    const tm_gauge *g = pr.g;
+    const size_t b64 = spinor_field_bytes(TM_FP64, g->vh, g->nf, pr.nrhs);
+    char name[64];
+    auto vec = [&](const char *tag, size_t bytes) -> void * {
+        snprintf(name, sizeof(name), "cg_%s_%d", tag, slot);
+        return workspace(ctx, name, bytes, &rc);
+    };
+    pr.c = vec("c", b64);
+    pr.y = vec("y", b64);
+    if (!pr.c || !pr.y) return rc;
+    if (inner == TM_FP64) {
+        pr.r64 = vec("r", b64);
+        pr.p64 = vec("p", b64);
+        pr.mp64 = vec("mp", b64);
+        pr.ap64 = vec("ap", b64);
+        if (!pr.r64 || !pr.p64 || !pr.mp64 || !pr.ap64) return rc;
+    } else {
+        const size_t bl = spinor_field_bytes(inner, g->vh, g->nf, pr.nrhs);
+        pr.rlo = vec("rlo", bl);
+        pr.plo = vec("plo", bl);
+        pr.mplo = vec("mplo", bl);
+        pr.aplo = vec("aplo", bl);
+        pr.xlo = vec("xlo", spinor_field_bytes(TM_FP32, g->vh, g->nf, pr.nrhs));
+        if (!pr.rlo || !pr.plo || !pr.mplo || !pr.aplo || !pr.xlo) return rc;
+    }
+    pr.cg = (CGScalars *)vec("scalars", sizeof(CGScalars) * pr.nrhs);
+    pr.dres = (double *)vec("dres", sizeof(double) * 2 * pr.nrhs);
+    if (!pr.cg || !pr.dres) return rc;
+    return TM_OK;
+}
+
+// norms of n problems' vectors (FP64 fields) into host array out[prob][rhs]
+int norms_fp64(tm_ctx *ctx, std::vector<CGProblem> &pr, void *const *v, std::vector<std::vector<double>> &out)
+{
+    const int n = (int)pr.size();
+    BlasCall calls[kMaxProblems];
+    for (int i = 0; i < n; i++)
+        calls[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {v[i], nullptr, nullptr, nullptr}, FIN_STORE,
+                            nullptr, pr[i].dres};
+    TM_TRY(launch_blas_batch(ctx, OP_NORM2, TM_FP64, TM_FP64, pr[0].g->nf, calls, n));
+    int total = 0;
+    for (auto &p : pr) total += p.nrhs;
+    int rc = TM_OK;
+    double *h = host_scratch(ctx, total, &rc);
+    if (!h) return rc;
+    int off = 0;
+    for (int i = 0; i < n; i++) {
+        TM_HIP(ctx, hipMemcpyAsync(h + off, pr[i].dres, pr[i].nrhs * sizeof(double),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        off += pr[i].nrhs;
+    }
+    TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    out.assign(n, {});
+    off = 0;
+    for (int i = 0; i < n; i++) {
+        out[i].assign(h + off, h + off + pr[i].nrhs);
+        off += pr[i].nrhs;
+    }
+    return TM_OK;
+}
+
+int read_scalars(tm_ctx *ctx, std::vector<CGProblem> &pr, std::vector<std::vector<CGScalars>> &out)
+{
+    const int n = (int)pr.size();
+    int total = 0;
+    for (auto &p : pr) total += p.nrhs;
+    int rc = TM_OK;
+    double *h = host_scratch(ctx, total * sizeof(CGScalars) / sizeof(double), &rc);
+    if (!h) return rc;
+    CGScalars *hs = (CGScalars *)h;
+    int off = 0;
+    for (int i = 0; i < n; i++) {
+        TM_HIP(ctx, hipMemcpyAsync(hs + off, pr[i].cg, pr[i].nrhs * sizeof(CGScalars),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        off += pr[i].nrhs;
+    }
+    TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    out.assign(n, {});
+    off = 0;
+    for (int i = 0; i < n; i++) {
+        out[i].assign(hs + off, hs + off + pr[i].nrhs);
+        off += pr[i].nrhs;
+    }
+    return TM_OK;
+}
+
+// Normal operator in FP64 on all problems: out = M^+ M in (mid: M in)
+int normal_op64(tm_ctx *ctx, std::vector<CGProblem> &pr, int pc, void *const *out, void *const *mid,
+                const void *const *in)
+{
+    const int n = (int)pr.size();
+    const tm_gauge *gs[kMaxProblems];
+    int nr[kMaxProblems];
+    for (int i = 0; i < n; i++) {
+        gs[i] = pr[i].g;
+        nr[i] = pr[i].nrhs;
+    }
+    TM_TRY(mat_pc_batch(ctx, gs, mid, in, nr, n, TM_FP64, pc, 0, FIN_NONE, nullptr));
+    TM_TRY(mat_pc_batch(ctx, gs, out, (const void *const *)mid, nr, n, TM_FP64, pc, 1, FIN_NONE, nullptr));
+    return TM_OK;
+}
+
+// r = c - A x (FP64) written to r (precision rp) and, if p given, to p; the
+// norm finishes with `fin` into the CG scalars (or dres when fin == FIN_STORE).
+int true_residual(tm_ctx *ctx, std::vector<CGProblem> &pr, int pc, int rp, void *const *r,
+                  void *const *p, int fin)
+{
+    const int n = (int)pr.size();
+    void *ys[kMaxProblems], *mids[kMaxProblems];
+    const void *xs[kMaxProblems];
+    for (int i = 0; i < n; i++) {
+        ys[i] = pr[i].y;
+        xs[i] = pr[i].x;
+        int rc = TM_OK;
+        char name[64];
+        snprintf(name, sizeof(name), "cg_mid_%d", i);
+        mids[i] = workspace(ctx, name, spinor_field_bytes(TM_FP64, pr[i].g->vh, pr[i].g->nf, pr[i].nrhs), &rc);
+        if (!mids[i]) return rc;
+    }
+    TM_TRY(normal_op64(ctx, pr, pc, ys, mids, xs));
+    BlasCall calls[kMaxProblems];
+    for (int i = 0; i < n; i++)
+        calls[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].c, pr[i].y, r[i], p ? p[i] : nullptr},
+                            fin, pr[i].cg, pr[i].dres};
+    return launch_blas_batch(ctx, OP_RESIDUAL, TM_FP64, rp, pr[0].g->nf, calls, n);
+}
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    ~GraphCache()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// The CG driver over n problems (plain FP64 or mixed with reliable updates).
+int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_cg_result *res)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = (int)pr.size();
+    const int pc = par->pc;
+    const int inner = par->inner;
+    const bool mixed = inner != TM_FP64;
+    const double delta = par->delta > 0 ? par->delta : 0.1;
+    const int check_every = std::max(1, par->check_every);
+    const int nf = pr[0].g->nf;
+
+    for (int i = 0; i < n; i++) TM_TRY(cg_setup_vectors(ctx, pr[i], i, inner));
+    // Every buffer an iteration touches exists before any graph capture: the
+    // reduction slots at their largest size and the odd temporaries.
+    for (int i = 0; i < n; i++) {
+        RedSlot rs;
+        const size_t need = std::max<size_t>(((pr[i].g->vh + 127) / 128) * pr[i].nrhs,
+                                             (size_t)2048 * pr[i].nrhs);
+        TM_TRY(red_slot(ctx, i, need, &rs));
+        int rc = TM_OK;
+        if (!odd_tmp(ctx, i, pr[i].g, TM_FP64, pr[i].nrhs, &rc)) return rc;
+        if (!odd_tmp(ctx, i, pr[i].g, inner, pr[i].nrhs, &rc)) return rc;
+    }
+
+    const tm_gauge *gs[kMaxProblems];
+    int nr[kMaxProblems];
+    for (int i = 0; i < n; i++) {
+        gs[i] = pr[i].g;
+        nr[i] = pr[i].nrhs;
+    }
+    // c = M^+ b
+    {
+        void *cs[kMaxProblems];
+        const void *bs[kMaxProblems];
+        for (int i = 0; i < n; i++) {
+            cs[i] = pr[i].c;
+            bs[i] = pr[i].b;
+        }
+        TM_TRY(mat_pc_batch(ctx, gs, cs, bs, nr, n, TM_FP64, pc, 1, FIN_NONE, nullptr));
+        std::vector<std::vector<double>> cc;
+        TM_TRY(norms_fp64(ctx, pr, cs, cc));
+        for (int i = 0; i < n; i++)
+            for (int r = 0; r < pr[i].nrhs; r++) {
+                pr[i].cc[r] = cc[i][r];
+                if (!std::isfinite(cc[i][r])) return fail(ctx, TM_ERR_NAN, "non-finite source norm");
+            }
+    }
+    // scalars
+    {
+        int rc = TM_OK;
+        int total = 0;
+        for (auto &p : pr) total += p.nrhs;
+        double *h = host_scratch(ctx, total * sizeof(CGScalars) / sizeof(double) + 1, &rc);
+        if (!h) return rc;
+        CGScalars *hs = (CGScalars *)h;
+        int off = 0;
+        for (int i = 0; i < n; i++) {
+            for (int r = 0; r < pr[i].nrhs; r++) {
+                CGScalars s{};
+                s.stop2 = par->tol * par->tol * pr[i].cc[r];
+                s.active = pr[i].cc[r] > 0 ? 1 : 0;
+                hs[off + r] = s;
+            }
+            TM_HIP(ctx, hipMemcpyAsync(pr[i].cg, hs + off, pr[i].nrhs * sizeof(CGScalars),
+                                       hipMemcpyHostToDevice, ctx->stream));
+            off += pr[i].nrhs;
+        }
+        TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (!par->use_x0)
+        for (int i = 0; i < n; i++)
+            TM_HIP(ctx, hipMemsetAsync(pr[i].x, 0, spinor_field_bytes(TM_FP64, pr[i].g->vh, nf, pr[i].nrhs),
+                                       ctx->stream));
+    if (mixed)
+        for (int i = 0; i < n; i++)
+            TM_HIP(ctx, hipMemsetAsync(pr[i].xlo, 0, spinor_field_bytes(TM_FP32, pr[i].g->vh, nf, pr[i].nrhs),
+                                       ctx->stream));
+
+    // initial residual r = c - A x (x = 0 or the guess), p = r
+    void *rv[kMaxProblems], *pv[kMaxProblems], *mpv[kMaxProblems], *apv[kMaxProblems], *xv[kMaxProblems];
+    for (int i = 0; i < n; i++) {
+        rv[i] = mixed ? pr[i].rlo : pr[i].r64;
+        pv[i] = mixed ? pr[i].plo : pr[i].p64;
+        mpv[i] = mixed ? pr[i].mplo : pr[i].mp64;
+        apv[i] = mixed ? pr[i].aplo : pr[i].ap64;
+        xv[i] = mixed ? pr[i].xlo : pr[i].x;
+    }
+    const int lp = mixed ? inner : TM_FP64;
+    const int xp = mixed ? TM_FP32 : TM_FP64;
+    TM_TRY(true_residual(ctx, pr, pc, lp, rv, pv, FIN_STORE_RR));
+
+    // one CG iteration over all problems, all stages batched
+    auto iteration = [&]() -> int {
+        CGScalars *cgs[kMaxProblems];
+        for (int i = 0; i < n; i++) cgs[i] = pr[i].cg;
+        TM_TRY(mat_pc_batch(ctx, gs, mpv, (const void *const *)pv, nr, n, lp, pc, 0, FIN_ALPHA, cgs));
+        TM_TRY(mat_pc_batch(ctx, gs, apv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_NONE, nullptr));
+        BlasCall up[kMaxProblems], xp_[kMaxProblems];
+        for (int i = 0; i < n; i++) {
+            up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], rv[i], apv[i]}, FIN_BETA, pr[i].cg, nullptr};
+            xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, nullptr, nullptr};
+        }
+        TM_TRY(launch_blas_batch(ctx, OP_CG_UPDATE, xp, lp, nf, up, n));
+        TM_TRY(launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n));
+        return TM_OK;
+    };
+
+    GraphCache gc;
+    const int gk = par->graph_iters;
+    if (gk > 0) {
+        TM_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        int rc = TM_OK;
+        for (int k = 0; k < gk && rc == TM_OK; k++) rc = iteration();
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+        if (rc != TM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(ctx, TM_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        gc.graph = graph;
+        TM_HIP(ctx, hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0));
+    }
+
+    int iters = 0, updates = 0;
+    std::vector<std::vector<CGScalars>> sc;
+    std::vector<std::vector<double>> maxrr(n);
+    TM_TRY(read_scalars(ctx, pr, sc));
+    for (int i = 0; i < n; i++) {
+        maxrr[i].resize(pr[i].nrhs);
+        for (int r = 0; r < pr[i].nrhs; r++) maxrr[i][r] = sc[i][r].rr;
+    }
+    bool done = false;
+    int status = TM_OK;
+    auto all_inactive = [&]() {
+        for (int i = 0; i < n; i++)
+            for (int r = 0; r < pr[i].nrhs; r++)
+                if (sc[i][r].active) return false;
+        return true;
+    };
+    done = all_inactive();
+    while (!done) {
+        int step = 0;
+        if (gk > 0) {
+            TM_HIP(ctx, hipGraphLaunch(gc.exec, ctx->stream));
+            step = gk;
+        } else {
+            const int m = mixed ? 1 : check_every;
+            for (int k = 0; k < m; k++) TM_TRY(iteration());
+            step = m;
+        }
+        iters += step;
+        TM_TRY(read_scalars(ctx, pr, sc));
+        bool need_update = false, bad = false;
+        for (int i = 0; i < n; i++)
+            for (int r = 0; r < pr[i].nrhs; r++) {
+                const CGScalars &s = sc[i][r];
+                if (!std::isfinite(s.rr) || !std::isfinite(s.alpha)) bad = true;
+                maxrr[i][r] = std::max(maxrr[i][r], s.rr);
+                if (mixed && s.active && s.rr < delta * delta * maxrr[i][r]) need_update = true;
+            }
+        if (bad) return fail(ctx, TM_ERR_NAN, "non-finite residual after %d iterations", iters);
+        const bool converged_lo = all_inactive();
+        if (mixed && (need_update || converged_lo)) {
+            // reliable update: x += x_lo; r = c - A x in FP64, rounded into r_lo
+            BlasCall acc[kMaxProblems];
+            for (int i = 0; i < n; i++)
+                acc[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, nullptr, nullptr}, FIN_NONE,
+                                  nullptr, nullptr};
+            TM_TRY(launch_blas_batch(ctx, OP_ACCUM_ZERO, TM_FP64, TM_FP32, nf, acc, n));
+            TM_TRY(true_residual(ctx, pr, pc, lp, rv, nullptr, FIN_RELIABLE));
+            // p = r + beta p with beta = |r_true|^2 / |r_prev|^2
+            BlasCall xp_[kMaxProblems];
+            for (int i = 0; i < n; i++)
+                xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, nullptr, nullptr};
+            TM_TRY(launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n));
+            updates++;
+            TM_TRY(read_scalars(ctx, pr, sc));
+            for (int i = 0; i < n; i++)
+                for (int r = 0; r < pr[i].nrhs; r++) maxrr[i][r] = sc[i][r].rr;
+            done = all_inactive();
+        } else if (!mixed && converged_lo) {
+            // verify with the true residual; restart from it if it is not small enough
+            TM_TRY(true_residual(ctx, pr, pc, TM_FP64, rv, pv, FIN_STORE_RR));
+            TM_TRY(read_scalars(ctx, pr, sc));
+            done = all_inactive();
+        }
+        if (!done && iters >= par->maxiter) {
+            status = TM_NOT_CONVERGED;
+            break;
+        }
+    }
+    if (mixed && status == TM_NOT_CONVERGED) {
+        BlasCall acc[kMaxProblems];
+        for (int i = 0; i < n; i++)
+            acc[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, nullptr, nullptr}, FIN_NONE,
+                              nullptr, nullptr};
+        TM_TRY(launch_blas_batch(ctx, OP_ACCUM_ZERO, TM_FP64, TM_FP32, nf, acc, n));
+    }
+    TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+
+    // reported residuals, recomputed in FP64 from x
+    std::vector<std::vector<double>> rn, rp, bb;
+    {
+        void *r64[kMaxProblems];
+        for (int i = 0; i < n; i++) {
+            int rc = TM_OK;
+            char name[64];
+            snprintf(name, sizeof(name), "cg_rtrue_%d", i);
+            r64[i] = workspace(ctx, name, spinor_field_bytes(TM_FP64, pr[i].g->vh, nf, pr[i].nrhs), &rc);
+            if (!r64[i]) return rc;
+        }
+        TM_TRY(true_residual(ctx, pr, pc, TM_FP64, r64, nullptr, FIN_NONE));
+        TM_TRY(norms_fp64(ctx, pr, r64, rn));
+        // |b - M x|: y = M x, r = b - y
+        void *ys[kMaxProblems];
+        const void *xs[kMaxProblems];
+        for (int i = 0; i < n; i++) {
+            ys[i] = pr[i].y;
+            xs[i] = pr[i].x;
+        }
+        TM_TRY(mat_pc_batch(ctx, gs, ys, xs, nr, n, TM_FP64, pc, 0, FIN_NONE, nullptr));
+        BlasCall calls[kMaxProblems];
+        for (int i = 0; i < n; i++)
+            calls[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].b, pr[i].y, r64[i], nullptr}, FIN_NONE,
+                                nullptr, nullptr};
+        TM_TRY(launch_blas_batch(ctx, OP_RESIDUAL, TM_FP64, TM_FP64, nf, calls, n));
+        TM_TRY(norms_fp64(ctx, pr, r64, rp));
+        void *bv[kMaxProblems];
+        for (int i = 0; i < n; i++) bv[i] = const_cast<void *>(pr[i].b);
+        TM_TRY(norms_fp64(ctx, pr, bv, bb));
+    }
+    int off = 0;
+    for (int i = 0; i < n; i++)
+        for (int r = 0; r < pr[i].nrhs; r++, off++) {
+            tm_cg_result &o = res[off];
+            o.iters = iters;
+            o.reliable_updates = updates;
+            o.true_rel_res_normal = pr[i].cc[r] > 0 ? std::sqrt(rn[i][r] / pr[i].cc[r]) : 0.0;
+            o.true_rel_res_pc = bb[i][r] > 0 ? std::sqrt(rp[i][r] / bb[i][r]) : 0.0;
+            o.seconds = secs;
+            if (!std::isfinite(o.true_rel_res_normal)) status = fail(ctx, TM_ERR_NAN, "non-finite residual");
+            if (status == TM_OK && o.true_rel_res_normal > par->tol * 1.0000001) status = TM_NOT_CONVERGED;
+        }
+    return status;
+}
+
+int check_cg(tm_ctx *ctx, const tm_gauge *g, const tm_cg_params *par)
+{
+    if (!par) return fail(ctx, TM_ERR_ARG, "null cg params");
+    if (!(par->tol > 0) || par->maxiter < 1) return fail(ctx, TM_ERR_ARG, "tol must be > 0, maxiter >= 1");
+    if (par->pc != TM_PC_ASYM && par->pc != TM_PC_SYM) return fail(ctx, TM_ERR_ARG, "bad pc type");
+    if (par->outer != TM_FP64) return fail(ctx, TM_ERR_PREC, "outer precision must be FP64");
+    if (!valid_prec(par->inner)) return fail(ctx, TM_ERR_PREC, "bad inner precision");
+    if (par->nrhs < 1 || par->nrhs > 64) return fail(ctx, TM_ERR_LIMIT, "nrhs must be in 1..64");
+    if (par->graph_iters < 0 || par->graph_iters > 256) return fail(ctx, TM_ERR_ARG, "graph_iters in 0..256");
+    TM_TRY(check_gauge_prec(ctx, g, TM_FP64));
+    TM_TRY(check_gauge_prec(ctx, g, par->inner));
+    return TM_OK;
+}
+
+}  // namespace
+
+namespace {
+// Graph capture needs a stream other than the null stream: for the duration of
+// a solve with graph_iters > 0 the context's work moves to a private stream
+// (ordered after the caller's stream, and the caller's stream after it).
+struct StreamSwap {
+    tm_ctx *ctx;
+    hipStream_t saved;
+    bool active = false;
+    StreamSwap(tm_ctx *c, bool want) : ctx(c), saved(c->stream)
+    {
+        if (!want || c->stream != nullptr) return;
+        if (!c->own_stream && hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
+            return;
+        (void)hipStreamSynchronize(saved);
+        c->stream = c->own_stream;
+        active = true;
+    }
+    ~StreamSwap()
+    {
+        if (!active) return;
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->stream = saved;
+    }
+};
+}  // namespace
+
+int tm_cg(tm_ctx *ctx, void *x_e, const void *b_e, const tm_gauge *g, const tm_cg_params *par,
+          tm_cg_result *res)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_cg(ctx, g, par));
+    if (!x_e || !b_e || !res) return fail(ctx, TM_ERR_ARG, "null pointer");
+    if (x_e == b_e) return fail(ctx, TM_ERR_ARG, "x and b must not alias");
+    std::vector<CGProblem> pr(1);
+    pr[0] = CGProblem{};
+    pr[0].g = g;
+    pr[0].nrhs = par->nrhs;
+    pr[0].x = x_e;
+    pr[0].b = b_e;
+    StreamSwap sw(ctx, par->graph_iters > 0);
+    return cg_run(ctx, pr, par, res);
+}
+
+int tm_cg_batched(tm_ctx *ctx, int nproblems, const tm_gauge *const *g, void *const *x_e,
+                  const void *const *b_e, const int *nrhs, const tm_cg_params *par, tm_cg_result *res)
+{
+    if (!ctx) return TM_ERR_ARG;
+    if (nproblems < 1 || nproblems > kMaxProblems)
+        return fail(ctx, TM_ERR_LIMIT, "nproblems must be in 1..%d", kMaxProblems);
+    if (!g || !x_e || !b_e || !nrhs || !res) return fail(ctx, TM_ERR_ARG, "null pointer");
+    std::vector<CGProblem> pr(nproblems);
+    for (int i = 0; i < nproblems; i++) {
+        tm_cg_params pi = *par;
+        pi.nrhs = nrhs[i];
+        TM_TRY(check_cg(ctx, g[i], &pi));
+        if (!x_e[i] || !b_e[i]) return fail(ctx, TM_ERR_ARG, "null field");
+        if (g[i]->nf != g[0]->nf || g[i]->recon != g[0]->recon)
+            return fail(ctx, TM_ERR_ARG, "batched problems must share flavour count and recon");
+        pr[i] = CGProblem{};
+        pr[i].g = g[i];
+        pr[i].nrhs = nrhs[i];
+        pr[i].x = x_e[i];
+        pr[i].b = b_e[i];
+    }
+    StreamSwap sw(ctx, par->graph_iters > 0);
+    return cg_run(ctx, pr, par, res);
+}
+
+int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm_gauge *g,
+             tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev)
+{
+    (void)F_dev; (void)force_prec; (void)X_e; (void)g; (void)prec; (void)pc; (void)coeff;
+    (void)accumulate; (void)G_dev;
+    if (!ctx) return TM_ERR_ARG;
+    return fail(ctx, TM_ERR_PREC, "force kernel not built");
+}
+
+}  // extern "C"

@@ -1,0 +1,360 @@
+// Fused Wilson twisted-mass hop kernel (Sec. 2.1: the hop fused with the local
+// twist R^-1 and with the kappa^2 xpay of Eqs. 2.2 / 2.3, for one flavour or
+// for the non-degenerate doublet with each link loaded once for both flavours).
+//
+// One thread computes one output site for NR right-hand sides and NF
+// flavours.  For every direction it loads the link (rebuilding row 2 from
+// rows 0, 1 when 12 reals are stored), loads the neighbour (only the spin
+// pair the time projector keeps, in the basis of Sec. 2), spin-projects to a
+// half spinor, multiplies by U or U^+, and rebuilds the lower spin pair.
+// The epilogue applies the twist / xpay of tm_epilogue and optionally adds
+// the squared norm of the output to a deterministic two-stage reduction.
+#pragma once
+
+#include "tm_fields.h"
+
+namespace twm {
+
+// Project, multiply by the link and accumulate one hop.
+//   SIG = +1: projector (1 - g_mu);  SIG = -1: projector (1 + g_mu)
+//   BWD: use U^+ (backward hop) instead of U.
+template <int MU, int SIG, bool BWD, typename T>
+__device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u)[3][3],
+                                               const cx<T> *v, T sgn)
+{
+    // v holds the 12 elements of the neighbour (or, for MU == 3, only the 6
+    // elements of the spin pair the projector keeps, at v[0..5]).
+    cx<T> h[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 0) {          // i s_1 psiL = (i psi3, i psi2)
+            if constexpr (SIG > 0) {
+                h[0][c] = v[c] + times_mi(v[9 + c]);
+                h[1][c] = v[3 + c] + times_mi(v[6 + c]);
+            } else {
+                h[0][c] = v[c] + times_i(v[9 + c]);
+                h[1][c] = v[3 + c] + times_i(v[6 + c]);
+            }
+        } else if constexpr (MU == 1) {   // i s_2 psiL = (psi3, -psi2)
+            if constexpr (SIG > 0) {
+                h[0][c] = v[c] - v[9 + c];
+                h[1][c] = v[3 + c] + v[6 + c];
+            } else {
+                h[0][c] = v[c] + v[9 + c];
+                h[1][c] = v[3 + c] - v[6 + c];
+            }
+        } else if constexpr (MU == 2) {   // i s_3 psiL = (i psi2, -i psi3)
+            if constexpr (SIG > 0) {
+                h[0][c] = v[c] + times_mi(v[6 + c]);
+                h[1][c] = v[3 + c] + times_i(v[9 + c]);
+            } else {
+                h[0][c] = v[c] + times_i(v[6 + c]);
+                h[1][c] = v[3 + c] + times_mi(v[9 + c]);
+            }
+        } else {                          // time: 2 psiL (SIG > 0) or 2 psiU
+            h[0][c] = v[c];
+            h[1][c] = v[3 + c];
+        }
+    }
+    const T f = (MU == 3) ? (T)2 * sgn : sgn;
+    cx<T> g[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cx<T> t;
+            if constexpr (!BWD) {
+                t = cmul(u[a][0], h[s][0]);
+                t = t + cmul(u[a][1], h[s][1]);
+                t = t + cmul(u[a][2], h[s][2]);
+            } else {
+                t = cjmul(u[0][a], h[s][0]);
+                t = t + cjmul(u[1][a], h[s][1]);
+                t = t + cjmul(u[2][a], h[s][2]);
+            }
+            g[s][a] = f * t;
+        }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 3) {
+            if constexpr (SIG > 0) {
+                acc[6 + c] = acc[6 + c] + g[0][c];
+                acc[9 + c] = acc[9 + c] + g[1][c];
+            } else {
+                acc[c] = acc[c] + g[0][c];
+                acc[3 + c] = acc[3 + c] + g[1][c];
+            }
+        } else {
+            acc[c] = acc[c] + g[0][c];
+            acc[3 + c] = acc[3 + c] + g[1][c];
+            // lower pair: SIG * i s_k g
+            if constexpr (MU == 0) {          // (i g1, i g0)
+                if constexpr (SIG > 0) {
+                    acc[6 + c] = acc[6 + c] + times_i(g[1][c]);
+                    acc[9 + c] = acc[9 + c] + times_i(g[0][c]);
+                } else {
+                    acc[6 + c] = acc[6 + c] + times_mi(g[1][c]);
+                    acc[9 + c] = acc[9 + c] + times_mi(g[0][c]);
+                }
+            } else if constexpr (MU == 1) {   // (g1, -g0)
+                if constexpr (SIG > 0) {
+                    acc[6 + c] = acc[6 + c] + g[1][c];
+                    acc[9 + c] = acc[9 + c] - g[0][c];
+                } else {
+                    acc[6 + c] = acc[6 + c] - g[1][c];
+                    acc[9 + c] = acc[9 + c] + g[0][c];
+                }
+            } else {                          // (i g0, -i g1)
+                if constexpr (SIG > 0) {
+                    acc[6 + c] = acc[6 + c] + times_i(g[0][c]);
+                    acc[9 + c] = acc[9 + c] + times_mi(g[1][c]);
+                } else {
+                    acc[6 + c] = acc[6 + c] + times_mi(g[0][c]);
+                    acc[9 + c] = acc[9 + c] + times_i(g[1][c]);
+                }
+            }
+        }
+    }
+}
+
+// One direction, forward (FWD) or backward, for all rhs and flavours.
+template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, int MU, bool FWD>
+__device__ __forceinline__ void hop_direction(cx<typename Prec<P>::real> (&acc)[NR][NF][12],
+                                              const HopProblem &pb, uint32_t nb, uint32_t link_cb,
+                                              int link_par, int r0, typename Prec<P>::real sgn)
+{
+    using real = typename Prec<P>::real;
+    constexpr int SIG = (FWD != DAG) ? 1 : -1;   // D: 1 - g forward; D^+ swaps
+    const uint32_t vh = pb.vh;
+    cx<real> u[3][3];
+    LinkIO<P, RECON>::load(u, pb.gauge[link_par], vh, MU, link_cb);
+    if constexpr (TWL) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<real> v[NF][12];
+#pragma unroll
+            for (int f = 0; f < NF; f++)
+                SpinorIO<P>::template load<0, 12>(v[f], pb.in, vh, (uint32_t)((r0 + r) * NF + f), nb);
+            apply_twist<real, NF>(v, pb.tw, true);
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                if constexpr (MU == 3)
+                    hop_accumulate<MU, SIG, !FWD>(acc[r][f], u, v[f] + (SIG > 0 ? 6 : 0), sgn);
+                else
+                    hop_accumulate<MU, SIG, !FWD>(acc[r][f], u, v[f], sgn);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                cx<real> v[12];
+                const uint32_t vec = (uint32_t)((r0 + r) * NF + f);
+                if constexpr (MU == 3) {
+                    if constexpr (SIG > 0)
+                        SpinorIO<P>::template load<6, 6>(v, pb.in, vh, vec, nb);
+                    else
+                        SpinorIO<P>::template load<0, 6>(v, pb.in, vh, vec, nb);
+                } else {
+                    SpinorIO<P>::template load<0, 12>(v, pb.in, vh, vec, nb);
+                }
+                hop_accumulate<MU, SIG, !FWD>(acc[r][f], u, v, sgn);
+            }
+    }
+}
+
+// Waves per SIMD the register allocation is held to (a 64-lane wave has 512
+// VGPRs per SIMD lane budget / waves).  Light variants get 4 (<= 128 VGPRs),
+// heavy ones (FP64, two flavours, several rhs) 2 (<= 256 VGPRs).
+template <int P, int NF, int NR>
+constexpr int hop_waves()
+{
+    return (P == TM_FP64 || NF * NR > 1) ? 2 : 4;
+}
+
+// Keeps the compiler from hoisting the loads of all eight hops ahead of the
+// arithmetic, which needs far more registers than the occupancy target
+// allows: the accumulators are pinned to registers at this point and no
+// memory access moves across it.
+template <typename T, int NR, int NF>
+__device__ __forceinline__ void dir_fence(cx<T> (&acc)[NR][NF][12])
+{
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int f = 0; f < NF; f++)
+#pragma unroll
+            for (int k = 0; k < 12; k++)
+                __asm__ volatile("" : "+v"(acc[r][f][k].re), "+v"(acc[r][f][k].im)::"memory");
+}
+#define TM_DIR_FENCE() dir_fence(acc)
+
+template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, int BS>
+__global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const HopBatch B)
+{
+    using real = typename Prec<P>::real;
+    __shared__ double red_sh[BS / 64];
+    __shared__ int last_sh;
+
+    const int lb = B.xcd_remap ? xcd_logical_block(blockIdx.x, B.total_blocks) : (int)blockIdx.x;
+    int pi = 0;
+    for (int i = 1; i < B.nprob; i++)
+        if (lb >= B.p[i].blk_start) pi = i;
+    const HopProblem &pb = B.p[pi];
+
+    const int lbl = lb - pb.blk_start;
+    const int sb = lbl / pb.ngrp;
+    const int grp = lbl - sb * pb.ngrp;
+    const int r0 = grp * NR;
+    const uint32_t cb = (uint32_t)sb * BS + threadIdx.x;
+    const uint32_t vh = pb.vh;
+    const bool valid = cb < vh;
+
+    double nrm[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) nrm[r] = 0.0;
+
+    if (valid) {
+        const int Lx = pb.X[0], Ly = pb.X[1], Lz = pb.X[2], Lt = pb.X[3];
+        const int xh_n = Lx >> 1;
+        const int xh = (int)(cb % xh_n);
+        int rest = (int)(cb / xh_n);
+        const int y = rest % Ly;
+        rest /= Ly;
+        const int z = rest % Lz;
+        const int t = rest / Lz;
+        const int par = pb.out_parity;
+        const int x = 2 * xh + ((y + z + t + par) & 1);
+        const uint32_t base = cb - xh;
+        const uint32_t sy = xh_n, sz = (uint32_t)xh_n * Ly, st = (uint32_t)xh_n * Ly * Lz;
+        const int npar = 1 - par;
+
+        cx<real> acc[NR][NF][12];
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+#pragma unroll
+            for (int f = 0; f < NF; f++)
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[r][f][k] = mk((real)0, (real)0);
+
+        const real one = (real)1;
+        // x direction
+        {
+            const int xp = (x + 1 == Lx) ? 0 : x + 1;
+            const int xm = (x == 0) ? Lx - 1 : x - 1;
+            const uint32_t nf_ = base + (xp >> 1), nb_ = base + (xm >> 1);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 0, true>(acc, pb, nf_, cb, par, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 0, false>(acc, pb, nb_, nb_, npar, r0, one);
+            TM_DIR_FENCE();
+        }
+        // y direction
+        {
+            const uint32_t nf_ = (y == Ly - 1) ? cb - (uint32_t)(Ly - 1) * sy : cb + sy;
+            const uint32_t nb_ = (y == 0) ? cb + (uint32_t)(Ly - 1) * sy : cb - sy;
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 1, true>(acc, pb, nf_, cb, par, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 1, false>(acc, pb, nb_, nb_, npar, r0, one);
+            TM_DIR_FENCE();
+        }
+        // z direction
+        {
+            const uint32_t nf_ = (z == Lz - 1) ? cb - (uint32_t)(Lz - 1) * sz : cb + sz;
+            const uint32_t nb_ = (z == 0) ? cb + (uint32_t)(Lz - 1) * sz : cb - sz;
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 2, true>(acc, pb, nf_, cb, par, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 2, false>(acc, pb, nb_, nb_, npar, r0, one);
+            TM_DIR_FENCE();
+        }
+        // t direction (boundary factor on hops across t = Lt-1 <-> 0)
+        {
+            const uint32_t nf_ = (t == Lt - 1) ? cb - (uint32_t)(Lt - 1) * st : cb + st;
+            const uint32_t nb_ = (t == 0) ? cb + (uint32_t)(Lt - 1) * st : cb - st;
+            const real sf = (t == Lt - 1) ? (real)pb.tsign : one;
+            const real sbk = (t == 0) ? (real)pb.tsign : one;
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 3, true>(acc, pb, nf_, cb, par, r0, sf);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, 3, false>(acc, pb, nb_, nb_, npar, r0, sbk);
+            TM_DIR_FENCE();
+        }
+
+        // epilogue
+        const real kk = (real)pb.k;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<real> (&A)[NF][12] = acc[r];
+            const int epi = B.epi;
+            if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) apply_twist<real, NF>(A, pb.tw, true);
+            if (epi >= TM_EPI_RX_PLUS_KD) {
+                cx<real> X[NF][12];
+#pragma unroll
+                for (int f = 0; f < NF; f++)
+                    SpinorIO<P>::template load<0, 12>(X[f], pb.x, vh, (uint32_t)((r0 + r) * NF + f), cb);
+                if (epi == TM_EPI_RX_PLUS_KD) apply_twist<real, NF>(X, pb.tw, false);
+#pragma unroll
+                for (int f = 0; f < NF; f++)
+#pragma unroll
+                    for (int k = 0; k < 12; k++) A[f][k] = X[f][k] + kk * A[f][k];
+                if (epi == TM_EPI_TWINV_X_PLUS_KD) apply_twist<real, NF>(A, pb.tw, true);
+            }
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                SpinorIO<P>::store(pb.out, vh, (uint32_t)((r0 + r) * NF + f), cb, A[f]);
+                if (pb.red.op != FIN_NONE) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 12; k++)
+                        s += (double)A[f][k].re * A[f][k].re + (double)A[f][k].im * A[f][k].im;
+                    nrm[r] += s;
+                }
+            }
+        }
+    }
+
+    if (pb.red.op != FIN_NONE) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const double s = block_sum<BS>(nrm[r], red_sh);
+            if (threadIdx.x == 0) pb.red.partials[(long)(r0 + r) * pb.nsb + sb] = s;
+        }
+        if (arrive_last(pb.red.counter, (unsigned)(pb.nsb * pb.ngrp), &last_sh))
+            finish_reduce<BS>(pb.red, pb.nrhs, pb.nsb, red_sh);
+    }
+}
+
+// Host-side dispatch over the compile-time variants built for precision P.
+
+#define TM_HOP_CASE(P, NF, NR, DAG, TWL, RECON, BS)                                            \
+    if (nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON && bs == BS) {   \
+        hipLaunchKernelGGL((hop_kernel<P, NF, NR, DAG, TWL, RECON, BS>), dim3(B.total_blocks), \
+                           dim3(BS), 0, st, B);                                                \
+        return hipGetLastError();                                                              \
+    }
+
+#define TM_HOP_CASES(P, NF, NR, RECON, BS) \
+    TM_HOP_CASE(P, NF, NR, 0, 0, RECON, BS)  \
+    TM_HOP_CASE(P, NF, NR, 1, 0, RECON, BS)
+
+#define TM_HOP_CASES_TWL(P, NF, NR, RECON) \
+    TM_HOP_CASE(P, NF, NR, 0, 1, RECON, 256) \
+    TM_HOP_CASE(P, NF, NR, 1, 1, RECON, 256)
+
+#define TM_HOP_DEFINE(P)                                                                       \
+    template <>                                                                                \
+    hipError_t launch_hop_prec<P>(const HopBatch &B, int nf, int nr, int dagger, int twl,      \
+                                  int recon, int bs, hipStream_t st)                           \
+    {                                                                                          \
+        TM_HOP_CASES(P, 1, 1, 12, 256)                                                         \
+        TM_HOP_CASES(P, 1, 1, 12, 128)                                                         \
+        TM_HOP_CASES(P, 1, 1, 18, 256)                                                         \
+        TM_HOP_CASES(P, 2, 1, 12, 256)                                                         \
+        TM_HOP_CASES(P, 2, 1, 12, 128)                                                         \
+        TM_HOP_CASES(P, 2, 1, 18, 256)                                                         \
+        TM_HOP_CASES(P, 1, 4, 12, 256)                                                         \
+        TM_HOP_CASES(P, 1, 4, 12, 128)                                                         \
+        TM_HOP_CASES_TWL(P, 1, 1, 12)                                                          \
+        TM_HOP_CASES_TWL(P, 1, 1, 18)                                                          \
+        TM_HOP_CASES_TWL(P, 2, 1, 12)                                                          \
+        TM_HOP_CASES_TWL(P, 2, 1, 18)                                                          \
+        TM_HOP_CASES_TWL(P, 1, 4, 12)                                                          \
+        return hipErrorInvalidConfiguration;                                                   \
+    }
+
+}  // namespace twm

@@ -1,0 +1,526 @@
+// Internal definitions shared by the HIP kernels and the host runtime.
+// Field layouts are those documented in include/tm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "../../include/tm.h"
+
+namespace twm {
+
+constexpr int kMaxProblems = 8;   // problems per batched launch
+constexpr int kBlock = 256;       // default threads per block
+
+// ------------------------------------------------------------------ complex
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cx<T> cjmul(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
+template <typename T>
+__device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.im, -a.re}; }
+
+// ------------------------------------------------------------------ precision
+
+template <int P>
+struct Prec;
+
+template <>
+struct Prec<TM_FP64> {
+    using real = double;
+    static constexpr int kChunkBytes = 16;   // one complex
+    static constexpr int kCplxPerChunk = 1;
+    static constexpr bool kScaled = false;
+};
+template <>
+struct Prec<TM_FP32> {
+    using real = float;
+    static constexpr int kChunkBytes = 16;   // two complex (float4)
+    static constexpr int kCplxPerChunk = 2;
+    static constexpr bool kScaled = false;
+};
+template <>
+struct Prec<TM_FP16> {
+    using real = float;
+    static constexpr int kChunkBytes = 8;    // two complex as four fp16
+    static constexpr int kCplxPerChunk = 2;
+    static constexpr bool kScaled = true;
+};
+template <>
+struct Prec<TM_BF16> {
+    using real = float;
+    static constexpr int kChunkBytes = 8;    // two complex as four bf16
+    static constexpr int kCplxPerChunk = 2;
+    static constexpr bool kScaled = true;
+};
+
+template <int P>
+constexpr int nchunks() { return 12 / Prec<P>::kCplxPerChunk; }
+
+// bytes of the chunk part of one parity field, rounded to 256
+__host__ __device__ inline size_t chunk_bytes(int prec, long vh, int nf, int nrhs)
+{
+    const size_t cb = (prec == TM_FP64 || prec == TM_FP32) ? 16 : 8;
+    const size_t nch = (prec == TM_FP64) ? 12 : 6;
+    size_t b = cb * nch * (size_t)vh * nf * nrhs;
+    return (b + 255) & ~(size_t)255;
+}
+__host__ __device__ inline size_t spinor_field_bytes(int prec, long vh, int nf, int nrhs)
+{
+    size_t b = chunk_bytes(prec, vh, nf, nrhs);
+    if (prec == TM_FP16 || prec == TM_BF16) b += (((size_t)vh * nf * nrhs * 4) + 255) & ~(size_t)255;
+    return b;
+}
+
+// fp16 / bf16 scalar conversions
+__device__ __forceinline__ float h2f(uint16_t h)
+{
+    _Float16 v;
+    __builtin_memcpy(&v, &h, 2);
+    return (float)v;
+}
+__device__ __forceinline__ uint16_t f2h(float f)
+{
+    _Float16 v = (_Float16)f;
+    uint16_t h;
+    __builtin_memcpy(&h, &v, 2);
+    return h;
+}
+__device__ __forceinline__ float b2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f2b(float f)
+{
+    // round to nearest even; inputs are finite and |f| <= 1 after scaling
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int P>
+__device__ __forceinline__ float half_to_f(uint16_t v)
+{
+    if constexpr (P == TM_FP16) return h2f(v); else return b2f(v);
+}
+template <int P>
+__device__ __forceinline__ uint16_t f_to_half(float v)
+{
+    if constexpr (P == TM_FP16) return f2h(v); else return f2b(v);
+}
+
+// ------------------------------------------------------------------ spinor access
+//
+// A parity field of nrhs x nf sites-vectors: chunk array + optional scales.
+// Site vector element k = 3*spin + colour.
+
+struct SpinorPtr {
+    void *data;      // chunk array
+    float *scale;    // per (rhs, flavour, site) scale (half precisions)
+};
+
+// Addressing: every (rhs, flavour, chunk) row starts at a wave-uniform base
+// pointer, and a lane adds the 32-bit offset cb * chunk bytes, so a load
+// needs one VGPR for the offset whatever the chunk (scalar base + vector
+// offset addressing).
+template <typename T>
+__device__ __forceinline__ const T *at(const void *base, uint32_t off)
+{
+    return (const T *)((const char *)base + off);
+}
+template <typename T>
+__device__ __forceinline__ T *at_w(void *base, uint32_t off)
+{
+    return (T *)((char *)base + off);
+}
+
+template <int P>
+struct SpinorIO {
+    using real = typename Prec<P>::real;
+    static constexpr int CB = Prec<P>::kChunkBytes;
+    static constexpr int NCH = nchunks<P>();
+
+    __device__ static __forceinline__ const char *row(const SpinorPtr &s, uint32_t vh, uint32_t vec,
+                                                      int chunk)
+    {
+        return (const char *)s.data + ((size_t)vec * NCH + chunk) * vh * CB;
+    }
+
+    // Load complex elements [K0, K0 + N) (multiples of the chunk size) of
+    // vector vec = rhs * nf + flavour at site cb.
+    template <int K0, int N>
+    __device__ static __forceinline__ void load(cx<real> *v, const SpinorPtr &s, uint32_t vh,
+                                                uint32_t vec, uint32_t cb)
+    {
+        const uint32_t off = cb * CB;
+        if constexpr (P == TM_FP64) {
+#pragma unroll
+            for (int k = 0; k < N; k++) {
+                double2 c = *at<double2>(row(s, vh, vec, K0 + k), off);
+                v[k] = mk(c.x, c.y);
+            }
+        } else if constexpr (P == TM_FP32) {
+#pragma unroll
+            for (int k = 0; k < N / 2; k++) {
+                float4 c = *at<float4>(row(s, vh, vec, K0 / 2 + k), off);
+                v[2 * k] = mk(c.x, c.y);
+                v[2 * k + 1] = mk(c.z, c.w);
+            }
+        } else {
+            const float sc = *at<float>(s.scale + (size_t)vec * vh, cb * 4u);
+#pragma unroll
+            for (int k = 0; k < N / 2; k++) {
+                uint2 c = *at<uint2>(row(s, vh, vec, K0 / 2 + k), off);
+                v[2 * k] = mk(sc * half_to_f<P>(c.x & 0xffff), sc * half_to_f<P>(c.x >> 16));
+                v[2 * k + 1] = mk(sc * half_to_f<P>(c.y & 0xffff), sc * half_to_f<P>(c.y >> 16));
+            }
+        }
+    }
+
+    // Store the full site vector (12 complex).
+    __device__ static __forceinline__ void store(const SpinorPtr &s, uint32_t vh, uint32_t vec,
+                                                 uint32_t cb, const cx<real> *v)
+    {
+        const uint32_t off = cb * CB;
+        if constexpr (P == TM_FP64) {
+#pragma unroll
+            for (int k = 0; k < 12; k++)
+                *at_w<double2>((void *)row(s, vh, vec, k), off) = make_double2(v[k].re, v[k].im);
+        } else if constexpr (P == TM_FP32) {
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                *at_w<float4>((void *)row(s, vh, vec, k), off) =
+                    make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+        } else {
+            float m = 0.f;
+#pragma unroll
+            for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+            const float inv = (m > 0.f) ? 1.0f / m : 0.f;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                uint2 c;
+                c.x = (uint32_t)f_to_half<P>(v[2 * k].re * inv) |
+                      ((uint32_t)f_to_half<P>(v[2 * k].im * inv) << 16);
+                c.y = (uint32_t)f_to_half<P>(v[2 * k + 1].re * inv) |
+                      ((uint32_t)f_to_half<P>(v[2 * k + 1].im * inv) << 16);
+                *at_w<uint2>((void *)row(s, vh, vec, k), off) = c;
+            }
+            *at_w<float>(s.scale + (size_t)vec * vh, cb * 4u) = m;
+        }
+    }
+};
+
+// Non-temporal vector loads (streamed data that is read once per launch).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 ld_nt(const double2 *p)
+{
+    nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_nt(const float4 *p)
+{
+    nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld_nt(const float2 *p)
+{
+    nt_f2 v = __builtin_nontemporal_load((const nt_f2 *)p);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ uint2 ld_nt(const uint2 *p)
+{
+    nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint32_t ld_nt(const uint32_t *p) { return __builtin_nontemporal_load(p); }
+
+// ------------------------------------------------------------------ links
+//
+// Links of one parity: [mu][elem-chunk][cb].  recon 12 stores rows 0, 1 (6
+// complex), recon 18 all 9.  Chunking: FP64 one complex per 16-byte chunk;
+// FP32 recon 12 two complex per float4, recon 18 one complex per float2;
+// FP16/BF16 recon 12 two complex per 8 bytes, recon 18 one complex per 4 bytes.
+
+__host__ __device__ inline size_t link_elem_bytes(int prec)
+{
+    return prec == TM_FP64 ? 16 : (prec == TM_FP32 ? 8 : 4);
+}
+__host__ __device__ inline size_t gauge_parity_bytes(int prec, int recon, long vh)
+{
+    size_t b = link_elem_bytes(prec) * (recon == 12 ? 6 : 9) * 4 * (size_t)vh;
+    return (b + 255) & ~(size_t)255;
+}
+
+template <int P, int RECON>
+struct LinkIO {
+    using real = typename Prec<P>::real;
+    static constexpr int NE = (RECON == 12) ? 6 : 9;
+
+    __device__ static __forceinline__ const char *row(const void *base, uint32_t vh, int mu,
+                                                      int chunk, int nch, int cbytes)
+    {
+        return (const char *)base + ((size_t)mu * nch + chunk) * vh * cbytes;
+    }
+
+    __device__ static __forceinline__ void load(cx<real> (&u)[3][3], const void *base, uint32_t vh,
+                                                int mu, uint32_t cb)
+    {
+        cx<real> e[9];
+        if constexpr (P == TM_FP64) {
+#pragma unroll
+            for (int k = 0; k < NE; k++) {
+                double2 c = ld_nt(at<double2>(row(base, vh, mu, k, NE, 16), cb * 16u));
+                e[k] = mk(c.x, c.y);
+            }
+        } else if constexpr (P == TM_FP32) {
+            if constexpr (RECON == 12) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    float4 c = ld_nt(at<float4>(row(base, vh, mu, k, 3, 16), cb * 16u));
+                    e[2 * k] = mk(c.x, c.y);
+                    e[2 * k + 1] = mk(c.z, c.w);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    float2 c = ld_nt(at<float2>(row(base, vh, mu, k, 9, 8), cb * 8u));
+                    e[k] = mk(c.x, c.y);
+                }
+            }
+        } else {
+            if constexpr (RECON == 12) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    uint2 c = ld_nt(at<uint2>(row(base, vh, mu, k, 3, 8), cb * 8u));
+                    e[2 * k] = mk(half_to_f<P>(c.x & 0xffff), half_to_f<P>(c.x >> 16));
+                    e[2 * k + 1] = mk(half_to_f<P>(c.y & 0xffff), half_to_f<P>(c.y >> 16));
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    uint32_t c = ld_nt(at<uint32_t>(row(base, vh, mu, k, 9, 4), cb * 4u));
+                    e[k] = mk(half_to_f<P>(c & 0xffff), half_to_f<P>(c >> 16));
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) u[a][b] = e[3 * a + b];
+        if constexpr (RECON == 12) {
+            // third row of an SU(3) matrix: conj(row0 x row1)
+            u[2][0] = conjg(cmul(u[0][1], u[1][2]) - cmul(u[0][2], u[1][1]));
+            u[2][1] = conjg(cmul(u[0][2], u[1][0]) - cmul(u[0][0], u[1][2]));
+            u[2][2] = conjg(cmul(u[0][0], u[1][1]) - cmul(u[0][1], u[1][0]));
+        } else {
+#pragma unroll
+            for (int b = 0; b < 3; b++) u[2][b] = e[6 + b];
+        }
+    }
+};
+
+// ------------------------------------------------------------------ twist
+//
+// R v = v + i ta g5 t3 v + b t1 v;  R^-1 v = c (v - i ta g5 t3 v - b t1 v),
+// c = 1 / (1 + ta^2 - b^2).  ta carries the flavour sign (one flavour) and the
+// dagger sign.  g5 swaps the upper (k < 6) and lower (k >= 6) spin pairs.
+struct Twist {
+    double ta, b, c;
+};
+
+template <typename T, int NF>
+__device__ __forceinline__ void apply_twist(cx<T> (&v)[NF][12], const Twist &tw, bool inverse)
+{
+    const T ta = (T)tw.ta, b = (T)tw.b;
+    const T s = inverse ? (T)-1 : (T)1;
+    const T c = inverse ? (T)tw.c : (T)1;
+    cx<T> o[NF][12];
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+        const T t3 = (f == 0) ? ta : -ta;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const int kk = (k < 6) ? k + 6 : k - 6;
+            cx<T> r = v[f][k] + (s * t3) * times_i(v[f][kk]);
+            if constexpr (NF == 2) r = r + (s * b) * v[1 - f][k];
+            o[f][k] = c * r;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) v[f][k] = o[f][k];
+}
+
+// ------------------------------------------------------------------ reductions
+
+// CG scalars per right-hand side, device resident.
+struct CGScalars {
+    double rr;       // |r|^2 of the iterated residual
+    double rr_old;
+    double pap;      // |M p|^2 = <p, M^+ M p>
+    double alpha;
+    double beta;
+    double stop2;    // stop when rr <= stop2
+    int active;      // 0 once converged (updates become no-ops)
+    int pad;
+};
+
+enum FinOp { FIN_NONE = 0, FIN_STORE = 1, FIN_ALPHA = 2, FIN_BETA = 3, FIN_STORE_RR = 4, FIN_RELIABLE = 5 };
+
+struct Reduce {
+    double *partials;      // [nvec][nblk]
+    unsigned *counter;     // one per launch (reset by the last block)
+    double *out;           // FIN_STORE destination [nvec]
+    CGScalars *cg;         // FIN_ALPHA / FIN_BETA state [nvec]
+    int op;
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the block; result valid in thread 0.  Deterministic order.
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < BS / 64; i++) s += sh[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// Called by every thread of a block after thread 0 stored its partials.
+// Returns true in the block that arrives last; that block sees all partials.
+__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblk, int *flag_sh)
+{
+    __threadfence();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(counter, 1u);
+        *flag_sh = (prev == nblk - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag_sh != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Final reduction of partials[v][0..nblk) for v in [0, nvec) by one block,
+// then the finishing operation.  Fixed summation order.
+template <int BS>
+__device__ void finish_reduce(const Reduce &rd, int nvec, int nblk, double *sh)
+{
+    for (int v = 0; v < nvec; v++) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nblk; i += BS) s += rd.partials[(long)v * nblk + i];
+        s = block_sum<BS>(s, sh);
+        if (threadIdx.x == 0) {
+            if (rd.op == FIN_STORE) {
+                rd.out[v] = s;
+            } else if (rd.op == FIN_ALPHA) {
+                CGScalars &c = rd.cg[v];
+                c.pap = s;
+                c.alpha = (c.active && s > 0.0) ? c.rr / s : 0.0;
+            } else if (rd.op == FIN_BETA) {
+                CGScalars &c = rd.cg[v];
+                if (c.active) {
+                    c.beta = (c.rr > 0.0) ? s / c.rr : 0.0;
+                    c.rr_old = c.rr;
+                    c.rr = s;
+                    if (s <= c.stop2) c.active = 0;
+                } else {
+                    c.beta = 0.0;
+                }
+            } else if (rd.op == FIN_RELIABLE) {
+                // the residual was replaced by the true one (reliable update):
+                // continue the recurrence with beta = |r_true|^2 / |r_prev|^2
+                CGScalars &c = rd.cg[v];
+                c.beta = (c.rr_old > 0.0) ? s / c.rr_old : 0.0;
+                c.rr = s;
+                c.active = (s > c.stop2) ? 1 : 0;
+            } else if (rd.op == FIN_STORE_RR) {
+                // a fresh residual: restart the recurrence for this rhs
+                CGScalars &c = rd.cg[v];
+                c.rr = s;
+                c.rr_old = s;
+                c.beta = 0.0;
+                c.active = (s > c.stop2) ? 1 : 0;
+            }
+        }
+    }
+    if (threadIdx.x == 0) *rd.counter = 0u;
+}
+
+// ------------------------------------------------------------------ hop descriptors
+
+struct HopProblem {
+    int X[4];            // Lx, Ly, Lz, Lt
+    int vh;              // sites per parity
+    int nrhs;
+    int blk_start;       // first logical block of this problem
+    int nsb;             // site blocks
+    int ngrp;            // rhs groups
+    int out_parity;
+    double tsign;        // factor on hops across the t boundary
+    Twist tw;            // twist (dagger sign folded in)
+    double k;            // epilogue coefficient
+    const void *gauge[2];   // links of parity 0 / 1
+    SpinorPtr in, out, x;
+    Reduce red;
+};
+
+struct HopBatch {
+    int nprob;
+    int total_blocks;
+    int epi;             // tm_epilogue
+    int xcd_remap;       // 1: give every XCD a contiguous range of blocks
+    HopProblem p[kMaxProblems];
+};
+
+// Map hardware workgroup id to a logical block so that each of the 8 XCDs
+// (which receive workgroups round-robin) gets one contiguous range.
+__device__ __forceinline__ int xcd_logical_block(int i, int g)
+{
+    const int q = g >> 3, r = g & 7;
+    const int k = i & 7, j = i >> 3;
+    return k * q + (k < r ? k : r) + j;
+}
+
+}  // namespace twm
