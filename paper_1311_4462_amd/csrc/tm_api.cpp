@@ -272,6 +272,9 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         hp.out = sptr(c.out, prec, g->vh, nf, c.nrhs);
         hp.x = c.x ? sptr(c.x, prec, g->vh, nf, c.nrhs) : SpinorPtr{nullptr, nullptr};
         hp.red.op = c.fin;
+        if ((c.fin == FIN_ALPHA || c.fin == FIN_BETA || c.fin == FIN_STORE_RR || c.fin == FIN_RELIABLE) && !c.cg)
+            return fail(ctx, TM_ERR_ARG, "internal: hop reduction needs CG scalars");
+        if (c.fin == FIN_STORE && !c.red_out) return fail(ctx, TM_ERR_ARG, "internal: no reduction output");
         if (c.fin != FIN_NONE) {
             RedSlot rs;
             TM_TRY(red_slot(ctx, i, (size_t)hp.nsb * c.nrhs, &rs));
@@ -328,6 +331,12 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         for (int j = 0; j < 4; j++)
             bp.v[j] = c.v[j] ? sptr(c.v[j], vp[j], c.vh, nf, c.nrhs) : SpinorPtr{nullptr, nullptr};
         bp.red.op = c.fin;
+        bp.red.cg = c.cg;
+        // the CG update reads alpha and the xpay reads beta from the scalars
+        if ((op == OP_CG_UPDATE || op == OP_XPAY || c.fin == FIN_ALPHA || c.fin == FIN_BETA ||
+             c.fin == FIN_STORE_RR || c.fin == FIN_RELIABLE) && !c.cg)
+            return fail(ctx, TM_ERR_ARG, "internal: BLAS op %d needs CG scalars", op);
+        if (c.fin == FIN_STORE && !c.red_out) return fail(ctx, TM_ERR_ARG, "internal: no reduction output");
         if (c.fin != FIN_NONE) {
             RedSlot rs;
             TM_TRY(red_slot(ctx, i, (size_t)bp.nblk * c.nrhs * 2, &rs));
@@ -947,7 +956,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         BlasCall up[kMaxProblems], xp_[kMaxProblems];
         for (int i = 0; i < n; i++) {
             up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], rv[i], apv[i]}, FIN_BETA, pr[i].cg, nullptr};
-            xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, nullptr, nullptr};
+            xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg, nullptr};
         }
         TM_TRY(launch_blas_batch(ctx, OP_CG_UPDATE, xp, lp, nf, up, n));
         TM_TRY(launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n));
@@ -1021,7 +1030,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             // p = r + beta p with beta = |r_true|^2 / |r_prev|^2
             BlasCall xp_[kMaxProblems];
             for (int i = 0; i < n; i++)
-                xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, nullptr, nullptr};
+                xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg, nullptr};
             TM_TRY(launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n));
             updates++;
             TM_TRY(read_scalars(ctx, pr, sc));
