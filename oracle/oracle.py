@@ -277,3 +277,120 @@ def solve(p: Params, U, b, pc="asym", tol=1e-12, maxiter=10000):
     rhs = prepare(p, U, b, pc)
     x_e, info = cg(p, U, rhs, pc, tol, maxiter)
     return x_e + reconstruct(p, U, x_e, b), info
+
+
+# --- gauge force -------------------------------------------------------------
+#
+# S = phi^+ (M^+ M)^-1 phi with M the preconditioned operator on even sites.
+# A link variation U -> exp(w^a T^a) U, T^a = i lambda_a / 2, changes S by
+# dS/dw^a = f^a; the force is F = sum_a f^a T^a (traceless anti-Hermitian),
+# i.e. f^a = -2 tr(F T^a).  The unconstrained complex gradient G (the one
+# torch returns for a real function of complex U) obeys dS = Re tr(G^+ dU).
+
+def _gell_mann():
+    lam = np.zeros((8, 3, 3), dtype=np.complex128)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1], lam[1][1, 0] = -1j, 1j
+    lam[2][0, 0], lam[2][1, 1] = 1, -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2], lam[4][2, 0] = -1j, 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2], lam[6][2, 1] = -1j, 1j
+    lam[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+    return lam
+
+
+SU3_GENERATORS = 0.5j * _gell_mann()      # T^a, tr(T^a T^b) = -delta_ab / 2
+
+
+def action(p: Params, U, phi_e, pc="asym", tol=1e-14):
+    """S = <phi, (M^+ M)^-1 phi> (real) and X = (M^+ M)^-1 phi by FP64 CG."""
+    X = _cg_normal(p, U, phi_e, pc, tol)
+    return float(np.vdot(phi_e, X).real), X
+
+
+def _cg_normal(p, U, c, pc, tol, maxiter=100000):
+    """Plain CG on M^+ M X = c (c given directly)."""
+    x = np.zeros_like(c)
+    r = c.copy()
+    d = r.copy()
+    rr = _nrm2(r)
+    cc = _nrm2(c)
+    for _ in range(maxiter):
+        if rr <= tol * tol * cc:
+            break
+        mp = mat_pc(p, U, d, pc)
+        alpha = rr / _nrm2(mp)
+        x = x + alpha * d
+        r = r - alpha * mat_pc(p, U, mp, pc, dagger=True)
+        rr_new = _nrm2(r)
+        d = r + (rr_new / rr) * d
+        rr = rr_new
+    return x
+
+
+def force_product_rule(p: Params, U, X_e, links, pc="asym"):
+    """dS/dw^a for the listed links (mu, t, z, y, x) from the product rule
+    dM = -k^2 (dD_eo R_oo^-1 D_oe + D_eo R_oo^-1 dD_oe) (times R_ee^-1 for sym),
+    dS = -2 Re <M X, dM X>, with dD the hop built from the varied link alone
+    (D is linear in the links).  Returns F per listed link as [n, 3, 3]."""
+    Y = mat_pc(p, U, X_e, pc)
+    Z = twist(p, hop(p, U, X_e, ODD), inverse=True, parity=ODD)
+    out = []
+    for (mu, t, z, y, x) in links:
+        F = np.zeros((3, 3), dtype=np.complex128)
+        for a in range(8):
+            dU = np.zeros_like(U)
+            dU[mu, t, z, y, x] = SU3_GENERATORS[a] @ U[mu, t, z, y, x]
+            dmx = hop(p, dU, Z, EVEN) + hop(p, U, twist(p, hop(p, dU, X_e, ODD), inverse=True,
+                                                        parity=ODD), EVEN)
+            if pc == "sym":
+                dmx = twist(p, dmx, inverse=True, parity=EVEN)
+            dmx = -p.kappa ** 2 * dmx
+            f = -2.0 * np.vdot(Y, dmx).real
+            F += f * SU3_GENERATORS[a]
+        out.append(F)
+    return np.array(out)
+
+
+def _traceless_antiherm(m):
+    a = 0.5 * (m - np.swapaxes(m.conj(), -1, -2))
+    tr = np.trace(a, axis1=-2, axis2=-1)[..., None, None]
+    return a - tr / 3.0 * np.eye(3)
+
+
+def force(p: Params, U, X_e, pc="asym"):
+    """Force on every link from outer products of spinor fields:
+    with Y = M X, A = (Y or R_ee^-+ Y for sym) on even sites and
+    R_oo^-+ (D^+)_oe of that on odd sites, B = X on even and R_oo^-1 D_oe X on
+    odd sites, dS = 2 k^2 Re <A, dD B>, so for the link U_mu(x) with boundary
+    factor s
+      G = 2 k^2 s sum_{flavour, spin} [ (1 - g_mu) A(x) B(x+mu)^+ + B(x) ((1 + g_mu) A(x+mu))^+ ],
+      F = -1/2 T_A(U G^+).
+    Returns (F, G), complex [4, Lt, Lz, Ly, Lx, 3, 3]."""
+    Y = mat_pc(p, U, X_e, pc)
+    Ae = twist(p, Y, inverse=True, dagger=True, parity=EVEN) if pc == "sym" else Y
+    Wo = twist(p, hop(p, U, Ae, ODD, dagger=True), inverse=True, dagger=True, parity=ODD)
+    Zo = twist(p, hop(p, U, X_e, ODD), inverse=True, parity=ODD)
+    A = Ae + Wo
+    B = X_e + Zo
+    g = gammas()
+    lt = p.dims[3]
+    G = np.zeros_like(U)
+    for mu in range(4):
+        ax = 3 - mu                          # array axis of direction mu in [t, z, y, x]
+        Af = np.roll(A, -1, axis=ax)
+        Bf = np.roll(B, -1, axis=ax)
+        Pm = np.eye(4) - g[mu]
+        Pp = np.eye(4) + g[mu]
+        PmA = np.einsum("st,...ftc->...fsc", Pm, A)
+        PpAf = np.einsum("st,...ftc->...fsc", Pp, Af)
+        term = (np.einsum("...fsa,...fsb->...ab", PmA, Bf.conj())
+                + np.einsum("...fsa,...fsb->...ab", B, PpAf.conj()))
+        if mu == 3:
+            sb = np.ones(term.shape[:4])
+            sb[lt - 1] = p.tsign
+            term = term * sb[..., None, None]
+        G[mu] = 2.0 * p.kappa ** 2 * term
+    F = -0.5 * _traceless_antiherm(U @ np.swapaxes(G.conj(), -1, -2))
+    return F, G
