@@ -69,7 +69,7 @@ def cpu_baseline(U, b_e, dims, vh, budget_s=15.0):
                       f"{'x'.join(map(str, dims))} (median {t:.2f} s each)"}
 
 
-def cg_comparison(torch, api, inputs, reps=2):
+def cg_comparison(torch, api, inputs, reps=3):
     """32^3 x 64 doublet, mu = 0.15, eps = 0.19, kappa = 0.1615: FP64 CG vs mixed CG."""
     dims = (32, 32, 32, 64)
     p = api.make_params(dims, 0.1615, 0.15, 0.19, api.NDEG)
@@ -78,6 +78,7 @@ def cg_comparison(torch, api, inputs, reps=2):
     Ut = torch.from_numpy(U).cuda()
     del U
     ctx = api.Context()
+    ctx.set_tuning(True)
     g = api.Gauge(ctx, Ut, p, recon=12, precs=(api.FP64, api.FP32, api.FP16, api.BF16))
     del Ut
     b = inputs.gaussian_spinor(dims, 2, 2003)
@@ -113,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--cg-only", action="store_true", help="only the CG comparison")
+    ap.add_argument("--cg-reps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -128,12 +131,16 @@ def main():
     from paper_1311_4462_amd import api, inputs
 
     torch.cuda.set_device(0)
+    if a.cg_only:
+        print(json.dumps({"cg_32x32x32x64_nd": cg_comparison(torch, api, inputs, a.cg_reps)}), flush=True)
+        return
     dims = (24, 24, 24, 48)
     vh = int(np.prod(dims)) // 2
     p = api.make_params(dims, 0.1615, 0.004, 0.0, api.PLUS)
     log("bench: generating 24^3x48 links")
     U = inputs.gauge_field(dims, "near_unit", 1002)
     ctx = api.Context()
+    ctx.set_tuning(True)      # block size and link-load policy picked by timing, once per shape
     g = api.Gauge(ctx, torch.from_numpy(U).cuda(), p, recon=12, precs=(api.FP64, api.FP32))
     b = inputs.gaussian_spinor(dims, 1, 2002)
     from oracle import oracle as O  # only for the even projection of the CPU-baseline input
@@ -208,7 +215,7 @@ def main():
         cpu = cpu_baseline(Uc, b_e, dims, vh)
         del Uc
     if not a.no_cg:
-        extra["cg_32x32x32x64_nd"] = cg_comparison(torch, api, inputs)
+        extra["cg_32x32x32x64_nd"] = cg_comparison(torch, api, inputs, a.cg_reps)
 
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gflop/s", "n_gpus": 1,

@@ -34,6 +34,8 @@ struct tm_ctx {
     size_t host_scratch_bytes = 0;
     int tuning = 0;
     std::map<std::string, int> tuned;  // kernel key -> block size
+    int force_bs = 0;                  // TM_HOP_BS: fixed block size (0: tuned / default)
+    int force_lnt = -1;                // TM_LINK_NT: 1 / 0 fixes the link load policy
     int xcd_remap = 1;
 };
 
@@ -204,58 +206,101 @@ struct HopCall {
     double *red_out;
 };
 
-int choose_nr(int nf, int nrhs, int recon)
+// rhs per thread: 4 for one flavour, 12-real links, reduced precisions
+// (an FP64 site vector for 4 rhs alone needs 192 VGPRs)
+int choose_nr(int prec, int nf, int nrhs, int recon)
 {
-    if (nf == 1 && recon == 12 && nrhs % 4 == 0) return 4;
+    if (prec != TM_FP64 && nf == 1 && recon == 12 && nrhs % 4 == 0) return 4;
     return 1;
 }
 
-int choose_bs(tm_ctx *ctx, int prec, int nf, int nr, int twl, int recon)
+// Launch configurations instantiated for a hop variant (see TM_HOP_DEFINE):
+// block size, and whether links are loaded non-temporally (bypassing the
+// caches: best when the working set exceeds the 256 MB last-level cache) or
+// ordinarily (they can then stay cache resident across launches).
+struct HopCfg {
+    int bs;
+    bool lnt;
+};
+std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon)
 {
-    if (twl || recon != 12) return 256;
-    char key[64];
-    snprintf(key, sizeof(key), "hop_p%d_f%d_r%d_c%d", prec, nf, nr, recon);
-    auto it = ctx->tuned.find(key);
-    if (it != ctx->tuned.end()) return it->second;
-    return 256;
+    if (twl) return {{256, true}};
+    std::vector<int> bss = (recon != 12) ? std::vector<int>{256}
+                           : (nr == 1) ? std::vector<int>{64, 128, 256} : std::vector<int>{128, 256};
+    std::vector<HopCfg> out;
+    for (int b : bss) {
+        out.push_back({b, true});
+        out.push_back({b, false});
+    }
+    return out;
+}
+
+// Default when not tuned: 256 threads; ordinary link loads when the launch's
+// links and three spinor fields fit well inside the last-level cache.
+HopCfg default_cfg(int twl, size_t working_set)
+{
+    if (twl) return {256, true};
+    return {256, working_set > (size_t)200 << 20};
+}
+
+std::string tune_key(int prec, int nf, int nr, int dagger, int twl, int epi, int recon, long vh_total)
+{
+    char key[128];
+    snprintf(key, sizeof(key), "hop_p%d_f%d_r%d_d%d_t%d_e%d_c%d_v%ld", prec, nf, nr, dagger, twl, epi, recon,
+             vh_total);
+    return key;
+}
+
+void save_tune(tm_ctx *ctx, const std::string &key, int bs)
+{
+    const char *path = getenv("TM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d\n", key.c_str(), bs);
+    fclose(f);
+    (void)ctx;
+}
+
+void load_tune(tm_ctx *ctx)
+{
+    const char *path = getenv("TM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[160];
+    int bs;
+    while (fscanf(f, "%159s %d", key, &bs) == 2) ctx->tuned[key] = bs;
+    fclose(f);
 }
 
 hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger, int twl, int recon,
-                        int bs, hipStream_t st)
+                        int bs, bool lnt, hipStream_t st)
 {
     switch (prec) {
-    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, bs, st);
-    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, bs, st);
-    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, bs, st);
-    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, bs, st);
+    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
+    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
+    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
+    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
     }
     return hipErrorInvalidValue;
 }
 
 // One launch of the fused hop over up to kMaxProblems problems (same
 // precision, flavour count, recon, dagger, epilogue and rhs grouping).
-int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
+int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, HopBatch *B)
 {
-    if (n < 1 || n > kMaxProblems) return fail(ctx, TM_ERR_LIMIT, "too many problems in a batch");
-    const tm_gauge *g0 = calls[0].g;
-    const int prec = calls[0].prec, nf = g0->nf, recon = g0->recon;
-    int nr = 1 << 30;
-    for (int i = 0; i < n; i++) nr = std::min(nr, choose_nr(nf, calls[i].nrhs, recon));
-    for (int i = 0; i < n; i++)
-        if (calls[i].nrhs % nr) nr = 1;
-    const int bs = choose_bs(ctx, prec, nf, nr, calls[0].twl, recon);
-
-    HopBatch B;
-    memset(&B, 0, sizeof(B));
-    B.nprob = n;
-    B.epi = calls[0].epi;
-    B.xcd_remap = ctx->xcd_remap;
+    const int prec = calls[0].prec, nf = calls[0].g->nf;
+    memset(B, 0, sizeof(*B));
+    B->nprob = n;
+    B->epi = calls[0].epi;
+    B->xcd_remap = ctx->xcd_remap;
     int blocks = 0;
     for (int i = 0; i < n; i++) {
         const HopCall &c = calls[i];
         const tm_gauge *g = c.g;
         if (!g->links[prec][0]) return fail(ctx, TM_ERR_PREC, "gauge not built in precision %d", prec);
-        HopProblem &hp = B.p[i];
+        HopProblem &hp = B->p[i];
         for (int d = 0; d < 4; d++) hp.X[d] = g->p.dims[d];
         hp.vh = (int)g->vh;
         hp.nrhs = c.nrhs;
@@ -285,8 +330,73 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         }
         blocks += hp.nsb * hp.ngrp;
     }
-    B.total_blocks = blocks;
-    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, calls[0].dagger, calls[0].twl, recon, bs, ctx->stream));
+    B->total_blocks = blocks;
+    return TM_OK;
+}
+
+int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
+{
+    if (n < 1 || n > kMaxProblems) return fail(ctx, TM_ERR_LIMIT, "too many problems in a batch");
+    const tm_gauge *g0 = calls[0].g;
+    const int prec = calls[0].prec, nf = g0->nf, recon = g0->recon;
+    const int dagger = calls[0].dagger, twl = calls[0].twl;
+    int nr = 1 << 30;
+    for (int i = 0; i < n; i++) nr = std::min(nr, choose_nr(prec, nf, calls[i].nrhs, recon));
+    for (int i = 0; i < n; i++)
+        if (calls[i].nrhs % nr) nr = 1;
+    const std::vector<HopCfg> cand = cfg_candidates(nr, twl, recon);
+    long vh_total = 0;
+    size_t wset = 0;
+    for (int i = 0; i < n; i++) {
+        const tm_gauge *g = calls[i].g;
+        vh_total += (long)g->vh * calls[i].nrhs;
+        wset += 2 * gauge_parity_bytes(prec, recon, g->vh) + 3 * spinor_field_bytes(prec, g->vh, nf, calls[i].nrhs);
+    }
+    HopCfg cfg = default_cfg(twl, wset);
+    const std::string key = tune_key(prec, nf, nr, dagger, twl, calls[0].epi, recon, vh_total);
+    auto it = ctx->tuned.find(key);
+    if (ctx->force_bs || ctx->force_lnt >= 0) {
+        HopCfg want{ctx->force_bs ? ctx->force_bs : cfg.bs, ctx->force_lnt >= 0 ? ctx->force_lnt != 0 : cfg.lnt};
+        for (const HopCfg &c : cand)
+            if (c.bs == want.bs && c.lnt == want.lnt) cfg = want;
+    } else if (it != ctx->tuned.end()) {
+        cfg = HopCfg{it->second & 0xffff, (it->second >> 16) != 0};
+    } else if (ctx->tuning && cand.size() > 1) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        (void)hipStreamIsCapturing(ctx->stream, &cs);
+        if (cs == hipStreamCaptureStatusNone) {
+            // time every instantiated configuration on the real launch (hop
+            // launches are idempotent: out never aliases an input)
+            hipEvent_t e0, e1;
+            TM_HIP(ctx, hipEventCreate(&e0));
+            TM_HIP(ctx, hipEventCreate(&e1));
+            float best = 1e30f;
+            for (const HopCfg &c : cand) {
+                HopBatch B;
+                TM_TRY(build_hop_batch(ctx, calls, n, nr, c.bs, &B));
+                TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c.bs, c.lnt, ctx->stream));
+                TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
+                for (int r = 0; r < 4; r++)
+                    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c.bs, c.lnt, ctx->stream));
+                TM_HIP(ctx, hipEventRecord(e1, ctx->stream));
+                TM_HIP(ctx, hipEventSynchronize(e1));
+                float ms = 0.f;
+                TM_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    cfg = c;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0);
+            ctx->tuned[key] = code;
+            save_tune(ctx, key, code);
+        }
+    }
+    HopBatch B;
+    TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B));
+    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg.bs, cfg.lnt, ctx->stream));
     return TM_OK;
 }
 
@@ -444,6 +554,13 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
     const char *e = getenv("TM_XCD_REMAP");
     if (e) c->xcd_remap = atoi(e);
+    e = getenv("TM_HOP_BS");
+    if (e) c->force_bs = atoi(e);
+    e = getenv("TM_LINK_NT");
+    if (e) c->force_lnt = atoi(e) ? 1 : 0;
+    e = getenv("TM_TUNE");
+    if (e) c->tuning = atoi(e) ? 1 : 0;
+    load_tune(c);
     *ctx = c;
     return TM_OK;
 }
@@ -1191,10 +1308,41 @@ int tm_cg_batched(tm_ctx *ctx, int nproblems, const tm_gauge *const *g, void *co
 int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm_gauge *g,
              tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev)
 {
-    (void)F_dev; (void)force_prec; (void)X_e; (void)g; (void)prec; (void)pc; (void)coeff;
-    (void)accumulate; (void)G_dev;
     if (!ctx) return TM_ERR_ARG;
-    return fail(ctx, TM_ERR_PREC, "force kernel not built");
+    TM_TRY(check_gauge_prec(ctx, g, prec));
+    if (prec != TM_FP64 && prec != TM_FP32)
+        return fail(ctx, TM_ERR_PREC, "force fields must be FP64 or FP32");
+    if (force_prec != TM_FP64 && force_prec != TM_FP32)
+        return fail(ctx, TM_ERR_PREC, "force output must be FP64 or FP32");
+    if (!F_dev || !X_e) return fail(ctx, TM_ERR_ARG, "null pointer");
+    if (pc != TM_PC_ASYM && pc != TM_PC_SYM) return fail(ctx, TM_ERR_ARG, "bad pc type");
+    if (!std::isfinite(coeff)) return fail(ctx, TM_ERR_ARG, "non-finite coeff");
+    if (g->recon != 12 && g->recon != 18) return fail(ctx, TM_ERR_ARG, "bad recon");
+    int rc = TM_OK;
+    const size_t fb = spinor_field_bytes(prec, g->vh, g->nf, 1);
+    void *Y = workspace(ctx, "force_y", fb, &rc);
+    void *Ae = pc == TM_PC_SYM ? workspace(ctx, "force_ae", fb, &rc) : Y;
+    void *Zo = workspace(ctx, "force_z", fb, &rc);
+    void *Wo = workspace(ctx, "force_w", fb, &rc);
+    if (!Y || !Ae || !Zo || !Wo) return rc;
+    // Y = M X
+    const int one = 1;
+    TM_TRY(mat_pc_batch(ctx, &g, &Y, &X_e, &one, 1, prec, pc, 0, FIN_NONE, nullptr));
+    // A_e = Y (asym) or R_ee^-+ Y (sym)
+    if (pc == TM_PC_SYM)
+        TM_HIP(ctx, twist_apply(prec, g->nf, sptr(Ae, prec, g->vh, g->nf, 1), sptr(Y, prec, g->vh, g->nf, 1),
+                                g->vh, 1, make_twist(g->p, 1), 1, ctx->stream));
+    // Z_o = R_oo^-1 D_oe X;   W_o = R_oo^-+ (D^+)_oe A_e
+    TM_TRY(hop1(ctx, HopCall{g, prec, 1, 0, 0, TM_EPI_TWINV, X_e, Zo, nullptr, 0.0, 1, FIN_NONE,
+                             nullptr, nullptr}));
+    TM_TRY(hop1(ctx, HopCall{g, prec, 1, 1, 0, TM_EPI_TWINV, Ae, Wo, nullptr, 0.0, 1, FIN_NONE,
+                             nullptr, nullptr}));
+    SpinorPtr A[2] = {sptr(Ae, prec, g->vh, g->nf, 1), sptr(Wo, prec, g->vh, g->nf, 1)};
+    SpinorPtr B[2] = {sptr(X_e, prec, g->vh, g->nf, 1), sptr(Zo, prec, g->vh, g->nf, 1)};
+    TM_HIP(ctx, force_launch(prec, g->nf, force_prec, F_dev, G_dev, g->links[prec][0], g->links[prec][1],
+                             g->recon, A, B, g->p.dims, g->vh, g->p.t_antiperiodic ? -1.0 : 1.0, coeff,
+                             accumulate ? 1 : 0, g->p.kappa, ctx->stream));
+    return TM_OK;
 }
 
 }  // extern "C"

@@ -16,7 +16,7 @@ hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t v
 
 template <int P>
 hipError_t launch_hop_prec(const HopBatch &B, int nf, int nr, int dagger, int twl, int recon,
-                           int bs, hipStream_t st);
+                           int bs, bool lnt, hipStream_t st);
 
 // ---------------------------------------------------------------- BLAS
 
@@ -52,6 +52,6 @@ hipError_t launch_blas(int op, int pa, int pb, const BlasBatch &B, hipStream_t s
 hipError_t force_launch(int prec, int nf, int force_prec, void *F, void *G, const void *gauge0,
                         const void *gauge1, int recon, SpinorPtr A[2], SpinorPtr Bv[2],
                         const int *X, uint32_t vh, double tsign, double coeff, int accumulate,
-                        hipStream_t st);
+                        double kappa, hipStream_t st);
 
 }  // namespace twm

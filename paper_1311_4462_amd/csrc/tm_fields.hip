@@ -34,33 +34,9 @@ __global__ void gauge_pack_kernel(void *dst0, void *dst1, const double2 *src, Di
     const long V = 2L * vh;
     const long s = lex_of(cb, par, d.X);
     const double2 *u = src + ((long)mu * V + s) * 9;
-    void *dst = par ? dst1 : dst0;
-    constexpr int NE = RECON == 12 ? 6 : 9;
-    for (int k = 0; k < NE; k++) {
-        const double2 c = u[k];
-        const size_t idx = ((size_t)mu * NE + k) * vh + cb;   // element-major
-        if constexpr (P == TM_FP64) {
-            ((double2 *)dst)[idx] = c;
-        } else if constexpr (P == TM_FP32) {
-            if constexpr (RECON == 12) {
-                // two complex per float4 chunk: chunk k/2, half k%2
-                float *f = (float *)dst + (((size_t)mu * 3 + k / 2) * vh + cb) * 4 + (k % 2) * 2;
-                f[0] = (float)c.x;
-                f[1] = (float)c.y;
-            } else {
-                ((float2 *)dst)[idx] = make_float2((float)c.x, (float)c.y);
-            }
-        } else {
-            const uint16_t re = f_to_half<P>((float)c.x), im = f_to_half<P>((float)c.y);
-            if constexpr (RECON == 12) {
-                uint16_t *h = (uint16_t *)dst + (((size_t)mu * 3 + k / 2) * vh + cb) * 4 + (k % 2) * 2;
-                h[0] = re;
-                h[1] = im;
-            } else {
-                ((uint32_t *)dst)[idx] = (uint32_t)re | ((uint32_t)im << 16);
-            }
-        }
-    }
+    double2 e[9];
+    for (int k = 0; k < 9; k++) e[k] = u[k];
+    LinkIO<P, RECON>::store(par ? dst1 : dst0, vh, mu, cb, e);
 }
 
 hipError_t gauge_pack(int prec, int recon, void *dst0, void *dst1, const void *src, const int *X,

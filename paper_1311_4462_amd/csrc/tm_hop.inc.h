@@ -118,7 +118,7 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
 }
 
 // One direction, forward (FWD) or backward, for all rhs and flavours.
-template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, int MU, bool FWD>
+template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int MU, bool FWD>
 __device__ __forceinline__ void hop_direction(cx<typename Prec<P>::real> (&acc)[NR][NF][12],
                                               const HopProblem &pb, uint32_t nb, uint32_t link_cb,
                                               int link_par, int r0, typename Prec<P>::real sgn)
@@ -127,7 +127,7 @@ __device__ __forceinline__ void hop_direction(cx<typename Prec<P>::real> (&acc)[
     constexpr int SIG = (FWD != DAG) ? 1 : -1;   // D: 1 - g forward; D^+ swaps
     const uint32_t vh = pb.vh;
     cx<real> u[3][3];
-    LinkIO<P, RECON>::load(u, pb.gauge[link_par], vh, MU, link_cb);
+    LinkIO<P, RECON, LNT>::load(u, pb.gauge[link_par], vh, MU, link_cb);
     if constexpr (TWL) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
@@ -167,10 +167,13 @@ __device__ __forceinline__ void hop_direction(cx<typename Prec<P>::real> (&acc)[
 // Waves per SIMD the register allocation is held to (a 64-lane wave has 512
 // VGPRs per SIMD lane budget / waves).  Light variants get 4 (<= 128 VGPRs),
 // heavy ones (FP64, two flavours, several rhs) 2 (<= 256 VGPRs).
+#ifndef TM_HOP_WAVES_LIGHT
+#define TM_HOP_WAVES_LIGHT 4
+#endif
 template <int P, int NF, int NR>
 constexpr int hop_waves()
 {
-    return (P == TM_FP64 || NF * NR > 1) ? 2 : 4;
+    return (P == TM_FP64 && NF * NR == 1) ? 3 : (P == TM_FP64 || NF * NR > 1) ? 2 : TM_HOP_WAVES_LIGHT;
 }
 
 // Keeps the compiler from hoisting the loads of all eight hops ahead of the
@@ -188,9 +191,28 @@ __device__ __forceinline__ void dir_fence(cx<T> (&acc)[NR][NF][12])
             for (int k = 0; k < 12; k++)
                 __asm__ volatile("" : "+v"(acc[r][f][k].re), "+v"(acc[r][f][k].im)::"memory");
 }
-#define TM_DIR_FENCE() dir_fence(acc)
+// Fence granularity: 1 after each direction pair (forward + backward hop),
+// 2 after every hop (register-heavy variants: FP64, two flavours, several
+// rhs), 0 none.  TM_FENCE_MODE overrides it at build time.
+template <int P, int NF, int NR>
+constexpr int fence_mode()
+{
+#ifdef TM_FENCE_MODE
+    return TM_FENCE_MODE;
+#else
+    return (P == TM_FP64 || NF * NR > 1) ? 2 : 1;
+#endif
+}
+#define TM_DIR_FENCE()                                   \
+    do {                                                 \
+        if (fence_mode<P, NF, NR>() != 0) dir_fence(acc); \
+    } while (0)
+#define TM_HOP_FENCE()                                   \
+    do {                                                 \
+        if (fence_mode<P, NF, NR>() == 2) dir_fence(acc); \
+    } while (0)
 
-template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, int BS>
+template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int BS>
 __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const HopBatch B)
 {
     using real = typename Prec<P>::real;
@@ -244,24 +266,27 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
             const int xp = (x + 1 == Lx) ? 0 : x + 1;
             const int xm = (x == 0) ? Lx - 1 : x - 1;
             const uint32_t nf_ = base + (xp >> 1), nb_ = base + (xm >> 1);
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 0, true>(acc, pb, nf_, cb, par, r0, one);
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 0, false>(acc, pb, nb_, nb_, npar, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, true>(acc, pb, nf_, cb, par, r0, one);
+            TM_HOP_FENCE();
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, false>(acc, pb, nb_, nb_, npar, r0, one);
             TM_DIR_FENCE();
         }
         // y direction
         {
             const uint32_t nf_ = (y == Ly - 1) ? cb - (uint32_t)(Ly - 1) * sy : cb + sy;
             const uint32_t nb_ = (y == 0) ? cb + (uint32_t)(Ly - 1) * sy : cb - sy;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 1, true>(acc, pb, nf_, cb, par, r0, one);
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 1, false>(acc, pb, nb_, nb_, npar, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, true>(acc, pb, nf_, cb, par, r0, one);
+            TM_HOP_FENCE();
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, false>(acc, pb, nb_, nb_, npar, r0, one);
             TM_DIR_FENCE();
         }
         // z direction
         {
             const uint32_t nf_ = (z == Lz - 1) ? cb - (uint32_t)(Lz - 1) * sz : cb + sz;
             const uint32_t nb_ = (z == 0) ? cb + (uint32_t)(Lz - 1) * sz : cb - sz;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 2, true>(acc, pb, nf_, cb, par, r0, one);
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 2, false>(acc, pb, nb_, nb_, npar, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, true>(acc, pb, nf_, cb, par, r0, one);
+            TM_HOP_FENCE();
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, false>(acc, pb, nb_, nb_, npar, r0, one);
             TM_DIR_FENCE();
         }
         // t direction (boundary factor on hops across t = Lt-1 <-> 0)
@@ -270,8 +295,9 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
             const uint32_t nb_ = (t == 0) ? cb + (uint32_t)(Lt - 1) * st : cb - st;
             const real sf = (t == Lt - 1) ? (real)pb.tsign : one;
             const real sbk = (t == 0) ? (real)pb.tsign : one;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 3, true>(acc, pb, nf_, cb, par, r0, sf);
-            hop_direction<P, NF, NR, DAG, TWL, RECON, 3, false>(acc, pb, nb_, nb_, npar, r0, sbk);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, true>(acc, pb, nf_, cb, par, r0, sf);
+            TM_HOP_FENCE();
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, false>(acc, pb, nb_, nb_, npar, r0, sbk);
             TM_DIR_FENCE();
         }
 
@@ -321,39 +347,48 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
 
 // Host-side dispatch over the compile-time variants built for precision P.
 
-#define TM_HOP_CASE(P, NF, NR, DAG, TWL, RECON, BS)                                            \
-    if (nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON && bs == BS) {   \
-        hipLaunchKernelGGL((hop_kernel<P, NF, NR, DAG, TWL, RECON, BS>), dim3(B.total_blocks), \
-                           dim3(BS), 0, st, B);                                                \
-        return hipGetLastError();                                                              \
+#define TM_HOP_CASE(P, NF, NR, DAG, TWL, RECON, LNT, BS)                                          \
+    if (nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON && lnt == LNT &&      \
+        bs == BS) {                                                                                 \
+        hipLaunchKernelGGL((hop_kernel<P, NF, NR, DAG, TWL, RECON, LNT, BS>), dim3(B.total_blocks), \
+                           dim3(BS), 0, st, B);                                                     \
+        return hipGetLastError();                                                                   \
     }
 
-#define TM_HOP_CASES(P, NF, NR, RECON, BS) \
-    TM_HOP_CASE(P, NF, NR, 0, 0, RECON, BS)  \
-    TM_HOP_CASE(P, NF, NR, 1, 0, RECON, BS)
+// both daggers, both link-load policies
+#define TM_HOP_CASES(P, NF, NR, RECON, BS)          \
+    TM_HOP_CASE(P, NF, NR, 0, 0, RECON, true, BS)  \
+    TM_HOP_CASE(P, NF, NR, 1, 0, RECON, true, BS)  \
+    TM_HOP_CASE(P, NF, NR, 0, 0, RECON, false, BS) \
+    TM_HOP_CASE(P, NF, NR, 1, 0, RECON, false, BS)
 
-#define TM_HOP_CASES_TWL(P, NF, NR, RECON) \
-    TM_HOP_CASE(P, NF, NR, 0, 1, RECON, 256) \
-    TM_HOP_CASE(P, NF, NR, 1, 1, RECON, 256)
+// twist-on-load variants: non-temporal links, 256 threads
+#define TM_HOP_CASES_TWL(P, NF, NR, RECON)          \
+    TM_HOP_CASE(P, NF, NR, 0, 1, RECON, true, 256) \
+    TM_HOP_CASE(P, NF, NR, 1, 1, RECON, true, 256)
 
 #define TM_HOP_DEFINE(P)                                                                       \
     template <>                                                                                \
     hipError_t launch_hop_prec<P>(const HopBatch &B, int nf, int nr, int dagger, int twl,      \
-                                  int recon, int bs, hipStream_t st)                           \
+                                  int recon, int bs, bool lnt, hipStream_t st)                 \
     {                                                                                          \
         TM_HOP_CASES(P, 1, 1, 12, 256)                                                         \
         TM_HOP_CASES(P, 1, 1, 12, 128)                                                         \
+        TM_HOP_CASES(P, 1, 1, 12, 64)                                                          \
         TM_HOP_CASES(P, 1, 1, 18, 256)                                                         \
         TM_HOP_CASES(P, 2, 1, 12, 256)                                                         \
         TM_HOP_CASES(P, 2, 1, 12, 128)                                                         \
+        TM_HOP_CASES(P, 2, 1, 12, 64)                                                          \
         TM_HOP_CASES(P, 2, 1, 18, 256)                                                         \
-        TM_HOP_CASES(P, 1, 4, 12, 256)                                                         \
-        TM_HOP_CASES(P, 1, 4, 12, 128)                                                         \
+        if constexpr (P != TM_FP64) {                                                          \
+            TM_HOP_CASES(P, 1, 4, 12, 256)                                                     \
+            TM_HOP_CASES(P, 1, 4, 12, 128)                                                     \
+            TM_HOP_CASES_TWL(P, 1, 4, 12)                                                      \
+        }                                                                                      \
         TM_HOP_CASES_TWL(P, 1, 1, 12)                                                          \
         TM_HOP_CASES_TWL(P, 1, 1, 18)                                                          \
         TM_HOP_CASES_TWL(P, 2, 1, 12)                                                          \
         TM_HOP_CASES_TWL(P, 2, 1, 18)                                                          \
-        TM_HOP_CASES_TWL(P, 1, 4, 12)                                                          \
         return hipErrorInvalidConfiguration;                                                   \
     }
 

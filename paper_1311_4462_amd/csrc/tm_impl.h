@@ -68,15 +68,15 @@ struct Prec<TM_FP32> {
 template <>
 struct Prec<TM_FP16> {
     using real = float;
-    static constexpr int kChunkBytes = 8;    // two complex as four fp16
-    static constexpr int kCplxPerChunk = 2;
+    static constexpr int kChunkBytes = 16;   // four complex as eight fp16
+    static constexpr int kCplxPerChunk = 4;
     static constexpr bool kScaled = true;
 };
 template <>
 struct Prec<TM_BF16> {
     using real = float;
-    static constexpr int kChunkBytes = 8;    // two complex as four bf16
-    static constexpr int kCplxPerChunk = 2;
+    static constexpr int kChunkBytes = 16;   // four complex as eight bf16
+    static constexpr int kCplxPerChunk = 4;
     static constexpr bool kScaled = true;
 };
 
@@ -86,9 +86,8 @@ constexpr int nchunks() { return 12 / Prec<P>::kCplxPerChunk; }
 // bytes of the chunk part of one parity field, rounded to 256
 __host__ __device__ inline size_t chunk_bytes(int prec, long vh, int nf, int nrhs)
 {
-    const size_t cb = (prec == TM_FP64 || prec == TM_FP32) ? 16 : 8;
-    const size_t nch = (prec == TM_FP64) ? 12 : 6;
-    size_t b = cb * nch * (size_t)vh * nf * nrhs;
+    const size_t nch = (prec == TM_FP64) ? 12 : (prec == TM_FP32 ? 6 : 3);   // 16-byte chunks
+    size_t b = 16 * nch * (size_t)vh * nf * nrhs;
     return (b + 255) & ~(size_t)255;
 }
 __host__ __device__ inline size_t spinor_field_bytes(int prec, long vh, int nf, int nrhs)
@@ -190,14 +189,36 @@ struct SpinorIO {
                 v[2 * k + 1] = mk(c.z, c.w);
             }
         } else {
+            // 16-byte chunks of four complex: elements 0-3 | 4-7 | 8-11; the
+            // upper spin pair (0-5) is chunk 0 and the low half of chunk 1.
             const float sc = *at<float>(s.scale + (size_t)vec * vh, cb * 4u);
+            if constexpr (K0 == 0 && N == 12) {
 #pragma unroll
-            for (int k = 0; k < N / 2; k++) {
-                uint2 c = *at<uint2>(row(s, vh, vec, K0 / 2 + k), off);
-                v[2 * k] = mk(sc * half_to_f<P>(c.x & 0xffff), sc * half_to_f<P>(c.x >> 16));
-                v[2 * k + 1] = mk(sc * half_to_f<P>(c.y & 0xffff), sc * half_to_f<P>(c.y >> 16));
+                for (int k = 0; k < 3; k++) unpack4(v + 4 * k, *at<uint4>(row(s, vh, vec, k), off), sc);
+            } else if constexpr (K0 == 0 && N == 6) {
+                unpack4(v, *at<uint4>(row(s, vh, vec, 0), off), sc);
+                unpack2(v + 4, *at<uint2>(row(s, vh, vec, 1), off), sc);
+            } else {
+                static_assert(K0 == 6 && N == 6, "half-precision loads: full site or one spin pair");
+                unpack2(v, *at<uint2>(row(s, vh, vec, 1), off + 8u), sc);
+                unpack4(v + 2, *at<uint4>(row(s, vh, vec, 2), off), sc);
             }
         }
+    }
+
+    __device__ static __forceinline__ void unpack2(cx<real> *v, uint2 c, float sc)
+    {
+        v[0] = mk(sc * half_to_f<P>(c.x & 0xffff), sc * half_to_f<P>(c.x >> 16));
+        v[1] = mk(sc * half_to_f<P>(c.y & 0xffff), sc * half_to_f<P>(c.y >> 16));
+    }
+    __device__ static __forceinline__ void unpack4(cx<real> *v, uint4 c, float sc)
+    {
+        unpack2(v, make_uint2(c.x, c.y), sc);
+        unpack2(v + 2, make_uint2(c.z, c.w), sc);
+    }
+    __device__ static __forceinline__ uint32_t pack1(cx<real> a, float inv)
+    {
+        return (uint32_t)f_to_half<P>(a.re * inv) | ((uint32_t)f_to_half<P>(a.im * inv) << 16);
     }
 
     // Store the full site vector (12 complex).
@@ -220,14 +241,10 @@ struct SpinorIO {
             for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
             const float inv = (m > 0.f) ? 1.0f / m : 0.f;
 #pragma unroll
-            for (int k = 0; k < 6; k++) {
-                uint2 c;
-                c.x = (uint32_t)f_to_half<P>(v[2 * k].re * inv) |
-                      ((uint32_t)f_to_half<P>(v[2 * k].im * inv) << 16);
-                c.y = (uint32_t)f_to_half<P>(v[2 * k + 1].re * inv) |
-                      ((uint32_t)f_to_half<P>(v[2 * k + 1].im * inv) << 16);
-                *at_w<uint2>((void *)row(s, vh, vec, k), off) = c;
-            }
+            for (int k = 0; k < 3; k++)
+                *at_w<uint4>((void *)row(s, vh, vec, k), off) =
+                    make_uint4(pack1(v[4 * k], inv), pack1(v[4 * k + 1], inv), pack1(v[4 * k + 2], inv),
+                               pack1(v[4 * k + 3], inv));
             *at_w<float>(s.scale + (size_t)vec * vh, cb * 4u) = m;
         }
     }
@@ -238,6 +255,7 @@ typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
 typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double2 ld_nt(const double2 *p)
 {
@@ -259,7 +277,22 @@ __device__ __forceinline__ uint2 ld_nt(const uint2 *p)
     nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
     return make_uint2(v.x, v.y);
 }
-__device__ __forceinline__ uint32_t ld_nt(const uint32_t *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ uint4 ld_nt(const uint4 *p)
+{
+    nt_u4 v = __builtin_nontemporal_load((const nt_u4 *)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t ld_nt(const uint32_t *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// Link loads: non-temporal (NT) or ordinary.
+template <bool NT, typename T>
+__device__ __forceinline__ T ldl(const T *p)
+{
+    if constexpr (NT) return ld_nt(p); else return *p;
+}
 
 // ------------------------------------------------------------------ links
 //
@@ -278,56 +311,74 @@ __host__ __device__ inline size_t gauge_parity_bytes(int prec, int recon, long v
     return (b + 255) & ~(size_t)255;
 }
 
-template <int P, int RECON>
+// Link rows of one parity (all [mu][cb], 16-byte rows first):
+//   FP64       NE rows of one complex (double2)
+//   FP32  12:  3 rows of two complex (float4)
+//   FP32  18:  4 rows of two complex (float4), then 1 row of one complex (float2)
+//   half  12:  1 row of four complex (16 B), then 1 row of two complex (8 B)
+//   half  18:  2 rows of four complex (16 B), then 1 row of one complex (4 B)
+template <int P, int RECON, bool NT = true>
 struct LinkIO {
     using real = typename Prec<P>::real;
     static constexpr int NE = (RECON == 12) ? 6 : 9;
 
-    __device__ static __forceinline__ const char *row(const void *base, uint32_t vh, int mu,
-                                                      int chunk, int nch, int cbytes)
+    // start of the 16-byte row k, and of the narrow tail row
+    __device__ static __forceinline__ const char *row16(const void *base, uint32_t vh, int mu, int k,
+                                                        int nrow)
     {
-        return (const char *)base + ((size_t)mu * nch + chunk) * vh * cbytes;
+        return (const char *)base + ((size_t)mu * nrow + k) * vh * 16;
+    }
+    __device__ static __forceinline__ const char *tail(const void *base, uint32_t vh, int mu, int nrow16,
+                                                       int tbytes)
+    {
+        return (const char *)base + (size_t)4 * nrow16 * vh * 16 + (size_t)mu * vh * tbytes;
+    }
+
+    __device__ static __forceinline__ cx<real> h2c(uint32_t c)
+    {
+        return mk(half_to_f<P>(c & 0xffff), half_to_f<P>(c >> 16));
     }
 
     __device__ static __forceinline__ void load(cx<real> (&u)[3][3], const void *base, uint32_t vh,
                                                 int mu, uint32_t cb)
     {
         cx<real> e[9];
+        const uint32_t o16 = cb * 16u;
         if constexpr (P == TM_FP64) {
 #pragma unroll
             for (int k = 0; k < NE; k++) {
-                double2 c = ld_nt(at<double2>(row(base, vh, mu, k, NE, 16), cb * 16u));
+                double2 c = ldl<NT>(at<double2>(row16(base, vh, mu, k, NE), o16));
                 e[k] = mk(c.x, c.y);
             }
         } else if constexpr (P == TM_FP32) {
-            if constexpr (RECON == 12) {
+            constexpr int NR = (RECON == 12) ? 3 : 4;
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    float4 c = ld_nt(at<float4>(row(base, vh, mu, k, 3, 16), cb * 16u));
-                    e[2 * k] = mk(c.x, c.y);
-                    e[2 * k + 1] = mk(c.z, c.w);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    float2 c = ld_nt(at<float2>(row(base, vh, mu, k, 9, 8), cb * 8u));
-                    e[k] = mk(c.x, c.y);
-                }
+            for (int k = 0; k < NR; k++) {
+                float4 c = ldl<NT>(at<float4>(row16(base, vh, mu, k, NR), o16));
+                e[2 * k] = mk(c.x, c.y);
+                e[2 * k + 1] = mk(c.z, c.w);
+            }
+            if constexpr (RECON == 18) {
+                float2 c = ldl<NT>(at<float2>(tail(base, vh, mu, 4, 8), cb * 8u));
+                e[8] = mk(c.x, c.y);
             }
         } else {
+            constexpr int NR = (RECON == 12) ? 1 : 2;
+#pragma unroll
+            for (int k = 0; k < NR; k++) {
+                uint4 c = ldl<NT>(at<uint4>(row16(base, vh, mu, k, NR), o16));
+                e[4 * k] = h2c(c.x);
+                e[4 * k + 1] = h2c(c.y);
+                e[4 * k + 2] = h2c(c.z);
+                e[4 * k + 3] = h2c(c.w);
+            }
             if constexpr (RECON == 12) {
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    uint2 c = ld_nt(at<uint2>(row(base, vh, mu, k, 3, 8), cb * 8u));
-                    e[2 * k] = mk(half_to_f<P>(c.x & 0xffff), half_to_f<P>(c.x >> 16));
-                    e[2 * k + 1] = mk(half_to_f<P>(c.y & 0xffff), half_to_f<P>(c.y >> 16));
-                }
+                uint2 c = ldl<NT>(at<uint2>(tail(base, vh, mu, 1, 8), cb * 8u));
+                e[4] = h2c(c.x);
+                e[5] = h2c(c.y);
             } else {
-#pragma unroll
-                for (int k = 0; k < 9; k++) {
-                    uint32_t c = ld_nt(at<uint32_t>(row(base, vh, mu, k, 9, 4), cb * 4u));
-                    e[k] = mk(half_to_f<P>(c & 0xffff), half_to_f<P>(c >> 16));
-                }
+                uint32_t c = ldl<NT>(at<uint32_t>(tail(base, vh, mu, 2, 4), cb * 4u));
+                e[8] = h2c(c);
             }
         }
 #pragma unroll
@@ -342,6 +393,37 @@ struct LinkIO {
         } else {
 #pragma unroll
             for (int b = 0; b < 3; b++) u[2][b] = e[6 + b];
+        }
+    }
+
+    // Write the stored elements (row-major, NE complex) of one link.
+    __device__ static __forceinline__ void store(void *base, uint32_t vh, int mu, uint32_t cb,
+                                                 const double2 *e)
+    {
+        char *b = (char *)base;
+        const uint32_t o16 = cb * 16u;
+        if constexpr (P == TM_FP64) {
+            for (int k = 0; k < NE; k++)
+                *at_w<double2>((void *)row16(b, vh, mu, k, NE), o16) = e[k];
+        } else if constexpr (P == TM_FP32) {
+            constexpr int NR = (RECON == 12) ? 3 : 4;
+            for (int k = 0; k < NR; k++)
+                *at_w<float4>((void *)row16(b, vh, mu, k, NR), o16) =
+                    make_float4((float)e[2 * k].x, (float)e[2 * k].y, (float)e[2 * k + 1].x, (float)e[2 * k + 1].y);
+            if constexpr (RECON == 18)
+                *at_w<float2>((void *)tail(b, vh, mu, 4, 8), cb * 8u) = make_float2((float)e[8].x, (float)e[8].y);
+        } else {
+            auto c2h = [](double2 v) {
+                return (uint32_t)f_to_half<P>((float)v.x) | ((uint32_t)f_to_half<P>((float)v.y) << 16);
+            };
+            constexpr int NR = (RECON == 12) ? 1 : 2;
+            for (int k = 0; k < NR; k++)
+                *at_w<uint4>((void *)row16(b, vh, mu, k, NR), o16) =
+                    make_uint4(c2h(e[4 * k]), c2h(e[4 * k + 1]), c2h(e[4 * k + 2]), c2h(e[4 * k + 3]));
+            if constexpr (RECON == 12)
+                *at_w<uint2>((void *)tail(b, vh, mu, 1, 8), cb * 8u) = make_uint2(c2h(e[4]), c2h(e[5]));
+            else
+                *at_w<uint32_t>((void *)tail(b, vh, mu, 2, 4), cb * 4u) = c2h(e[8]);
         }
     }
 };

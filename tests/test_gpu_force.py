@@ -1,0 +1,118 @@
+"""The hand-written force kernel and the autograd Function against the oracle's
+force and against central finite differences of the GPU-computed action.
+Tolerances: FP64 force 1e-10 relative (norm over links; the solve's 1e-12
+residual bounds it), FP32 force 1e-5."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1311_4462_amd import inputs
+from tests.gpu_util import from_native, oparams, rel, to_native
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_4462_amd import api
+    return torch, api
+
+
+def _solve_gpu(api, ctx, U, p, phi, pc, tol=1e-12):
+    g = api.Gauge(ctx, U, p, precs=(0, 1))
+    tb = to_native(api, ctx, phi, p, 0, 0)
+    x = api.new_field(p, 0)
+    res = api.tm_cg(ctx, x, tb, g, pc=pc, tol=tol)[0]
+    assert res["status"] == 0
+    return g, x
+
+
+@pytest.mark.parametrize("flavor,pc", [(2, 0), (1, 0), (2, 1), (-1, 1)])
+def test_force_kernel_matches_oracle(torch_api, flavor, pc):
+    torch, api = torch_api
+    ctx = api.Context()
+    dims = (4, 4, 4, 6)
+    p = api.make_params(dims, 0.1615, 0.15, 0.19 if flavor == 2 else 0.0, flavor)
+    op = oparams(p)
+    U = inputs.gauge_field(dims, "near_unit", 1005)
+    phi = O.project(inputs.gaussian_spinor(dims, op.nf, 2005), dims, 0)
+    g, x = _solve_gpu(api, ctx, U, p, phi, pc)
+    X = from_native(api, ctx, x, p, 0, 0)[0]
+    Fref, Gref = O.force(op, U, X, "asym" if pc == 0 else "sym")
+    for fp in (0, 1):
+        xf = x
+        if fp == 1:
+            xf = api.new_field(p, 1)
+            api.tm_convert(ctx, xf, 1, x, 0, p)
+        dt = torch.complex128 if fp == 0 else torch.complex64
+        F = torch.zeros(U.shape, dtype=dt, device="cuda")
+        G = torch.zeros(U.shape, dtype=dt, device="cuda")
+        api.tm_force(ctx, F, fp, xf, g, fp, pc, 1.0, False, G)
+        tol = 1e-10 if fp == 0 else 1e-5
+        assert rel(F.cpu().numpy(), Fref) < tol
+        assert rel(G.cpu().numpy(), Gref) < tol
+        # accumulate with a coefficient: F <- F + 0.5 F
+        api.tm_force(ctx, F, fp, xf, g, fp, pc, 0.5, True, None)
+        assert rel(F.cpu().numpy(), 1.5 * Fref) < tol
+    ctx.close()
+
+
+def test_force_c5_size_fp32_kernel(torch_api):
+    """16^3 x 32 doublet, kappa = 0.1615, mu = 0.15, eps = 0.19: FP64 solve,
+    FP32 force kernel, against the oracle's force from the same X."""
+    torch, api = torch_api
+    ctx = api.Context()
+    dims = (16, 16, 16, 32)
+    p = api.make_params(dims, 0.1615, 0.15, 0.19, 2)
+    op = oparams(p)
+    U = inputs.gauge_field(dims, "near_unit", 1005)
+    phi = O.project(inputs.gaussian_spinor(dims, 2, 2005), dims, 0)
+    g, x = _solve_gpu(api, ctx, U, p, phi, 0, tol=1e-10)
+    X = from_native(api, ctx, x, p, 0, 0)[0]
+    Fref, _ = O.force(op, U, X, "asym")
+    xf = api.new_field(p, 1)
+    api.tm_convert(ctx, xf, 1, x, 0, p)
+    F = torch.zeros(U.shape, dtype=torch.complex64, device="cuda")
+    api.tm_force(ctx, F, 1, xf, g, 1, 0, 1.0, False, None)
+    Fg = F.cpu().numpy().astype(np.complex128)
+    assert rel(Fg, Fref) < 1e-5
+    # traceless anti-Hermitian per link
+    assert np.abs(Fg + np.swapaxes(Fg.conj(), -1, -2)).max() < 1e-5 * np.abs(Fg).max()
+    assert np.abs(np.trace(Fg, axis1=-2, axis2=-1)).max() < 1e-5 * np.abs(Fg).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("force_prec", [0, 1])
+def test_autograd_action_gradient(torch_api, force_prec):
+    """TMAction: S matches the oracle, the gradient matches the oracle's G and
+    central differences of the GPU action along a random complex direction."""
+    torch, api = torch_api
+    from paper_1311_4462_amd.autograd import tm_action
+    dims = (4, 4, 4, 4)
+    p = api.make_params(dims, 0.1615, 0.15, 0.19, 2)
+    op = oparams(p)
+    Unp = inputs.gauge_field(dims, "near_unit", 1006)
+    phinp = O.project(inputs.gaussian_spinor(dims, 2, 2006), dims, 0)
+    U = torch.from_numpy(Unp).cuda().requires_grad_(True)
+    phi = torch.from_numpy(phinp).cuda().requires_grad_(True)
+    S = tm_action(U, phi, p, force_prec=force_prec)
+    Sref, Xref = O.action(op, Unp, phinp)
+    assert abs(S.item() - Sref) < 1e-10 * abs(Sref)
+    S.backward()
+    _, Gref = O.force(op, Unp, Xref)
+    tol = 1e-9 if force_prec == 0 else 1e-5
+    assert rel(U.grad.cpu().numpy(), Gref) < tol
+    assert rel(phi.grad.cpu().numpy(), 2 * Xref) < 1e-9
+    # finite differences of the GPU action, step 1e-5
+    rng = np.random.default_rng(3)
+    dU = rng.standard_normal(Unp.shape) + 1j * rng.standard_normal(Unp.shape)
+    h = 1e-5
+    with torch.no_grad():
+        Sp = tm_action(torch.from_numpy(Unp + h * dU).cuda(), phi.detach(), p, tol=1e-13).item()
+        Sm = tm_action(torch.from_numpy(Unp - h * dU).cuda(), phi.detach(), p, tol=1e-13).item()
+    fd = (Sp - Sm) / (2 * h)
+    an = float(np.sum(U.grad.cpu().numpy().conj() * dU).real)
+    assert abs(fd - an) <= (1e-6 if force_prec == 0 else 2e-5) * abs(an)
