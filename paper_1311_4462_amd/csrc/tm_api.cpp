@@ -40,7 +40,6 @@ struct tm_ctx {
 };
 
 struct tm_gauge {
-    tm_ctx *ctx = nullptr;
     tm_params p{};
     int recon = 12;
     int nf = 1;
@@ -602,7 +601,6 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const t
     if (recon != 12 && recon != 18) return fail(ctx, TM_ERR_ARG, "recon must be 12 or 18");
     if (prec_mask == 0 || (prec_mask & ~0xFu)) return fail(ctx, TM_ERR_PREC, "bad precision mask");
     tm_gauge *g = new tm_gauge();
-    g->ctx = ctx;
     g->p = *p;
     g->recon = recon;
     g->nf = nflav(*p);
@@ -635,7 +633,8 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const t
 int tm_gauge_destroy(tm_gauge *g)
 {
     if (!g) return TM_ERR_ARG;
-    if (g->ctx) (void)hipStreamSynchronize(g->ctx->stream);
+    // hipFree waits for outstanding device work; the gauge holds no reference
+    // to the context that built it, so either may be destroyed first.
     for (int prec = 0; prec < 4; prec++)
         for (int par = 0; par < 2; par++)
             if (g->links[prec][par]) (void)hipFree(g->links[prec][par]);

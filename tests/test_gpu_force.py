@@ -57,6 +57,7 @@ def test_force_kernel_matches_oracle(torch_api, flavor, pc):
         # accumulate with a coefficient: F <- F + 0.5 F
         api.tm_force(ctx, F, fp, xf, g, fp, pc, 0.5, True, None)
         assert rel(F.cpu().numpy(), 1.5 * Fref) < tol
+    g.close()
     ctx.close()
 
 
@@ -82,6 +83,7 @@ def test_force_c5_size_fp32_kernel(torch_api):
     # traceless anti-Hermitian per link
     assert np.abs(Fg + np.swapaxes(Fg.conj(), -1, -2)).max() < 1e-5 * np.abs(Fg).max()
     assert np.abs(np.trace(Fg, axis1=-2, axis2=-1)).max() < 1e-5 * np.abs(Fg).max()
+    g.close()
     ctx.close()
 
 
