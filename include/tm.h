@@ -29,12 +29,15 @@
  *   consecutive (spin, colour) complex numbers k = 3*spin + colour:
  *       TM_FP64: 16-byte chunks of 1 complex  (12 chunks per site)
  *       TM_FP32: 16-byte chunks of 2 complex  (6 chunks)
- *       TM_FP16 / TM_BF16: 8-byte chunks of 2 complex (6 chunks), followed
+ *       TM_FP16 / TM_BF16: 16-byte chunks of 4 complex (3 chunks), followed
  *       (at a 256-byte aligned offset) by a float scale per [rhs][flavour][cb];
  *       stored value = true value / scale, scale = max |real component| of
  *       the site's 24 reals for that flavour.
- *   Spin components 0, 1 (the "upper" pair) occupy the first half of the
- *   chunks, so a time hop reads only half of a neighbour.
+ *   Spin components 0, 1 (the "upper" pair, elements 0-5) occupy the first
+ *   half of the site's bytes, so a time hop reads only half of a neighbour.
+ *   Packed links (library owned): per parity [mu][cb] rows of 16 bytes, then
+ *   narrower rows for what does not fill 16 bytes; 12-real storage keeps rows
+ *   0 and 1 of each link.
  *   Canonical (host-side exchange) layout, complex128, full lattice:
  *       spinor [nrhs][lex][nf][4][3], links [mu][lex][3][3] (row-major).
  *
@@ -70,6 +73,10 @@ enum {
 typedef enum { TM_FP64 = 0, TM_FP32 = 1, TM_FP16 = 2, TM_BF16 = 3 } tm_prec;
 typedef enum { TM_TWIST_PLUS = 1, TM_TWIST_MINUS = -1, TM_TWIST_NDEG = 2 } tm_flavor;
 typedef enum { TM_PC_ASYM = 0, TM_PC_SYM = 1 } tm_pc;
+/* Solution type of the normal-equation solve (Sec. 2.2, solution_type):
+ * TM_SOLUTION_MAT: x solves M x = b (CG on M^+ M x = M^+ b);
+ * TM_SOLUTION_MATDAG_MAT: x solves M^+ M x = b.                              */
+typedef enum { TM_SOLUTION_MAT = 0, TM_SOLUTION_MATDAG_MAT = 1 } tm_solution;
 
 /* Epilogue of tm_dslash, with A = D in (or D^+ in), x the optional field of the
  * output parity and R, R^-1 daggered when dagger = 1:                          */
@@ -102,13 +109,14 @@ typedef struct {
     int nrhs;             /* right-hand sides solved together (>= 1)            */
     int graph_iters;      /* > 0: capture this many iterations in a hipGraph    */
     int check_every;      /* host convergence check period (0 -> 1)             */
+    int solution;         /* tm_solution                                        */
 } tm_cg_params;
 
 typedef struct {
     int iters;                    /* CG iterations performed                     */
     int reliable_updates;         /* FP64 residual replacements (mixed)          */
     double true_rel_res_normal;   /* |M^+b - M^+M x| / |M^+b|, FP64, recomputed  */
-    double true_rel_res_pc;       /* |b - M x| / |b|, FP64                       */
+    double true_rel_res_pc;       /* |b - M x| / |b| (MATDAG_MAT: |b - M^+M x|/|b|) */
     double seconds;               /* wall time of the solve (host clock)         */
 } tm_cg_result;
 
@@ -177,8 +185,9 @@ int tm_prepare(tm_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o, cons
 int tm_reconstruct_odd(tm_ctx *ctx, void *x_o, const void *x_e, const void *b_o,
                        const tm_gauge *g, tm_prec prec, int nrhs);
 
-/* CG on the normal equations M^+ M x = M^+ b of the preconditioned operator
- * (NORMOP_PC solve, Sec. 2.2).  x_e, b_e: native even fields in precision
+/* CG on the normal equations of the preconditioned operator (NORMOP_PC solve,
+ * Sec. 2.2): M^+ M x = M^+ b (solution TM_SOLUTION_MAT) or M^+ M x = b
+ * (TM_SOLUTION_MATDAG_MAT); tol applies to the residual of that system.  x_e, b_e: native even fields in precision
  * par->outer (TM_FP64), par->nrhs right-hand sides.  inner = TM_FP64: plain
  * FP64 CG; inner = FP32 / FP16 / BF16: mixed precision with reliable updates
  * (low-precision iterations; FP64 true residual, reductions and solution

@@ -25,7 +25,7 @@ class tm_params(ctypes.Structure):
 class tm_cg_params(ctypes.Structure):
     _fields_ = [("pc", c_int), ("tol", c_double), ("maxiter", c_int), ("outer", c_int),
                 ("inner", c_int), ("delta", c_double), ("use_x0", c_int), ("nrhs", c_int),
-                ("graph_iters", c_int), ("check_every", c_int)]
+                ("graph_iters", c_int), ("check_every", c_int), ("solution", c_int)]
 
 
 class tm_cg_result(ctypes.Structure):

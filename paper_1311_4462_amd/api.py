@@ -17,6 +17,7 @@ from ._lib import TMError, lib, tm_cg_params, tm_cg_result, tm_params
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 PLUS, MINUS, NDEG = 1, -1, 2
 ASYM, SYM = 0, 1
+SOLUTION_MAT, SOLUTION_MATDAG_MAT = 0, 1
 EPI_NONE, EPI_TWINV, EPI_RX_PLUS_KD, EPI_X_PLUS_K_TWINV_D, EPI_TWINV_X_PLUS_KD, EPI_X_PLUS_KD = range(6)
 TM_OK, TM_NOT_CONVERGED = 0, 1
 PREC_NAMES = {FP64: "f64", FP32: "f32", FP16: "f16", BF16: "bf16"}
@@ -192,8 +193,10 @@ def tm_reconstruct_odd(ctx, x_o, x_e, b_o, gauge: Gauge, prec, nrhs=1):
                                               nrhs), "tm_reconstruct_odd")
 
 
-def _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every):
+def _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every,
+               solution=0):
     p = tm_cg_params()
+    p.solution = solution
     p.pc, p.tol, p.maxiter, p.outer, p.inner = pc, tol, maxiter, FP64, inner
     p.delta, p.use_x0, p.nrhs, p.graph_iters, p.check_every = (delta, int(use_x0), nrhs,
                                                                graph_iters, check_every)
@@ -207,9 +210,9 @@ def _results(res, n):
 
 
 def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64, delta=0.1,
-          use_x0=False, nrhs=1, graph_iters=0, check_every=1):
+          use_x0=False, nrhs=1, graph_iters=0, check_every=1, solution=SOLUTION_MAT):
     """CG on the normal equations of the preconditioned operator; x_e, b_e FP64 native."""
-    p = _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every)
+    p = _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every, solution)
     res = (tm_cg_result * nrhs)()
     rc = ctx.check(lib().tm_cg(ctx.h, _ptr(x_e), _ptr(b_e), gauge.h, ctypes.byref(p), res), "tm_cg")
     out = _results(res, nrhs)
@@ -219,9 +222,9 @@ def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=F
 
 
 def tm_cg_batched(ctx, gauges, xs, bs, nrhs, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64,
-                  delta=0.1, graph_iters=0, check_every=1):
+                  delta=0.1, graph_iters=0, check_every=1, solution=SOLUTION_MAT):
     n = len(gauges)
-    p = _cg_params(pc, tol, maxiter, inner, delta, False, nrhs[0], graph_iters, check_every)
+    p = _cg_params(pc, tol, maxiter, inner, delta, False, nrhs[0], graph_iters, check_every, solution)
     ga = (ctypes.c_void_p * n)(*[g.h.value for g in gauges])
     xa = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
     ba = (ctypes.c_void_p * n)(*[_ptr(b) for b in bs])

@@ -31,7 +31,8 @@ def _solve(ctx, U, phi, params, pc, tol, recon, precs):
     phi_n = api.tm_spinor_pack(ctx, phi.detach().reshape((1,) + tuple(phi.shape)).contiguous(),
                                params, api.FP64, 0)
     x = api.new_field(params, api.FP64)
-    res = api.tm_cg(ctx, x, phi_n, g, pc=pc, tol=tol, maxiter=100000)[0]
+    res = api.tm_cg(ctx, x, phi_n, g, pc=pc, tol=tol, maxiter=100000,
+                    solution=api.SOLUTION_MATDAG_MAT)[0]
     if res["status"] != 0:
         raise RuntimeError(f"TMAction: solve did not converge: {res}")
     return g, phi_n, x, res

@@ -1002,7 +1002,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         gs[i] = pr[i].g;
         nr[i] = pr[i].nrhs;
     }
-    // c = M^+ b
+    // c = M^+ b (solution MAT) or c = b (MATDAG_MAT)
     {
         void *cs[kMaxProblems];
         const void *bs[kMaxProblems];
@@ -1010,7 +1010,15 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             cs[i] = pr[i].c;
             bs[i] = pr[i].b;
         }
-        TM_TRY(mat_pc_batch(ctx, gs, cs, bs, nr, n, TM_FP64, pc, 1, FIN_NONE, nullptr));
+        if (par->solution == TM_SOLUTION_MATDAG_MAT) {
+            BlasCall cp[kMaxProblems];
+            for (int i = 0; i < n; i++)
+                cp[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].b, pr[i].c, nullptr, nullptr}, FIN_NONE,
+                                 nullptr, nullptr};
+            TM_TRY(launch_blas_batch(ctx, OP_CONVERT, TM_FP64, TM_FP64, nf, cp, n));
+        } else {
+            TM_TRY(mat_pc_batch(ctx, gs, cs, bs, nr, n, TM_FP64, pc, 1, FIN_NONE, nullptr));
+        }
         std::vector<std::vector<double>> cc;
         TM_TRY(norms_fp64(ctx, pr, cs, cc));
         for (int i = 0; i < n; i++)
@@ -1187,14 +1195,16 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         }
         TM_TRY(true_residual(ctx, pr, pc, TM_FP64, r64, nullptr, FIN_NONE));
         TM_TRY(norms_fp64(ctx, pr, r64, rn));
-        // |b - M x|: y = M x, r = b - y
+        // |b - M x|: y = M x, r = b - y  (MATDAG_MAT: y = M^+ M x, left in y by the
+        // residual above)
         void *ys[kMaxProblems];
         const void *xs[kMaxProblems];
         for (int i = 0; i < n; i++) {
             ys[i] = pr[i].y;
             xs[i] = pr[i].x;
         }
-        TM_TRY(mat_pc_batch(ctx, gs, ys, xs, nr, n, TM_FP64, pc, 0, FIN_NONE, nullptr));
+        if (par->solution != TM_SOLUTION_MATDAG_MAT)
+            TM_TRY(mat_pc_batch(ctx, gs, ys, xs, nr, n, TM_FP64, pc, 0, FIN_NONE, nullptr));
         BlasCall calls[kMaxProblems];
         for (int i = 0; i < n; i++)
             calls[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].b, pr[i].y, r64[i], nullptr}, FIN_NONE,
@@ -1229,6 +1239,8 @@ int check_cg(tm_ctx *ctx, const tm_gauge *g, const tm_cg_params *par)
     if (!valid_prec(par->inner)) return fail(ctx, TM_ERR_PREC, "bad inner precision");
     if (par->nrhs < 1 || par->nrhs > 64) return fail(ctx, TM_ERR_LIMIT, "nrhs must be in 1..64");
     if (par->graph_iters < 0 || par->graph_iters > 256) return fail(ctx, TM_ERR_ARG, "graph_iters in 0..256");
+    if (par->solution != TM_SOLUTION_MAT && par->solution != TM_SOLUTION_MATDAG_MAT)
+        return fail(ctx, TM_ERR_ARG, "bad solution type");
     TM_TRY(check_gauge_prec(ctx, g, TM_FP64));
     TM_TRY(check_gauge_prec(ctx, g, par->inner));
     return TM_OK;
