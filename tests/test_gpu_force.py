@@ -108,13 +108,30 @@ def test_autograd_action_gradient(torch_api, force_prec):
     tol = 1e-9 if force_prec == 0 else 1e-5
     assert rel(U.grad.cpu().numpy(), Gref) < tol
     assert rel(phi.grad.cpu().numpy(), 2 * Xref) < 1e-9
-    # finite differences of the GPU action, step 1e-5
+    # finite differences of the GPU action, step 1e-5.  Along an arbitrary
+    # complex direction the links leave SU(3), so the action is evaluated with
+    # all 18 reals stored (12-real storage rebuilds row 2 assuming SU(3)).
     rng = np.random.default_rng(3)
     dU = rng.standard_normal(Unp.shape) + 1j * rng.standard_normal(Unp.shape)
     h = 1e-5
     with torch.no_grad():
-        Sp = tm_action(torch.from_numpy(Unp + h * dU).cuda(), phi.detach(), p, tol=1e-13).item()
-        Sm = tm_action(torch.from_numpy(Unp - h * dU).cuda(), phi.detach(), p, tol=1e-13).item()
+        Sp = tm_action(torch.from_numpy(Unp + h * dU).cuda(), phi.detach(), p, tol=1e-13, recon=18).item()
+        Sm = tm_action(torch.from_numpy(Unp - h * dU).cuda(), phi.detach(), p, tol=1e-13, recon=18).item()
     fd = (Sp - Sm) / (2 * h)
     an = float(np.sum(U.grad.cpu().numpy().conj() * dU).real)
+    assert abs(fd - an) <= (1e-6 if force_prec == 0 else 2e-5) * abs(an)
+    # along su(3) directions (U -> exp(h H) U stays in SU(3)) with 12-real links
+    w = rng.standard_normal((4,) + dims[::-1] + (8,))
+    H = np.einsum("...a,aij->...ij", w, O.SU3_GENERATORS)
+
+    def step(hh):
+        ev, V = np.linalg.eigh((-1j * hh * H).reshape(-1, 3, 3))
+        E = np.einsum("nij,nj,nkj->nik", V, np.exp(1j * ev), V.conj()).reshape(H.shape)
+        return torch.from_numpy(E @ Unp).cuda()
+
+    with torch.no_grad():
+        Sp = tm_action(step(h), phi.detach(), p, tol=1e-13).item()
+        Sm = tm_action(step(-h), phi.detach(), p, tol=1e-13).item()
+    fd = (Sp - Sm) / (2 * h)
+    an = float(np.sum(U.grad.cpu().numpy().conj() * (H @ Unp)).real)
     assert abs(fd - an) <= (1e-6 if force_prec == 0 else 2e-5) * abs(an)
