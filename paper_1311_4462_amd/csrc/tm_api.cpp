@@ -166,10 +166,9 @@ double *host_scratch(tm_ctx *ctx, size_t n, int *rc)
     return ctx->host_scratch;
 }
 
-// Reduction slot i: a counter and a partial-sum buffer (stream ordered, so
-// consecutive launches can share one slot; a batched launch uses one per problem).
+// Reduction slot i: a partial-sum buffer (stream ordered, so consecutive
+// launches can share one slot; a batched launch uses one per problem).
 struct RedSlot {
-    unsigned *counter;
     double *partials;
 };
 
@@ -177,9 +176,6 @@ int red_slot(tm_ctx *ctx, int i, size_t npartials, RedSlot *out)
 {
     int rc = TM_OK;
     char name[64];
-    snprintf(name, sizeof(name), "red_counter_%d", i);
-    out->counter = (unsigned *)workspace(ctx, name, 256, &rc);
-    if (!out->counter) return rc;
     snprintf(name, sizeof(name), "red_partials_%d", i);
     out->partials = (double *)workspace(ctx, name, std::max<size_t>(npartials, 64) * sizeof(double), &rc);
     if (!out->partials) return rc;
@@ -323,13 +319,32 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
             RedSlot rs;
             TM_TRY(red_slot(ctx, i, (size_t)hp.nsb * c.nrhs, &rs));
             hp.red.partials = rs.partials;
-            hp.red.counter = rs.counter;
             hp.red.cg = c.cg;
             hp.red.out = c.red_out;
+            hp.red.nvec = c.nrhs;
+            hp.red.nblk = hp.nsb;
         }
         blocks += hp.nsb * hp.ngrp;
     }
     B->total_blocks = blocks;
+    return TM_OK;
+}
+
+// The second stage of the reductions of a launch (one block per problem).
+template <typename Prob>
+int finish_reductions(tm_ctx *ctx, const Prob *p, int n)
+{
+    FinishBatch F;
+    memset(&F, 0, sizeof(F));
+    bool any = false;
+    for (int i = 0; i < n; i++) {
+        F.r[i] = p[i].red;
+        if (p[i].red.op != FIN_NONE) any = true;
+        else F.r[i].nvec = 0;
+    }
+    if (!any) return TM_OK;
+    F.nprob = n;
+    TM_HIP(ctx, launch_finish(F, ctx->stream));
     return TM_OK;
 }
 
@@ -396,6 +411,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     HopBatch B;
     TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B));
     TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg.bs, cfg.lnt, ctx->stream));
+    TM_TRY(finish_reductions(ctx, B.p, n));
     return TM_OK;
 }
 
@@ -450,14 +466,16 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
             RedSlot rs;
             TM_TRY(red_slot(ctx, i, (size_t)bp.nblk * c.nrhs * 2, &rs));
             bp.red.partials = rs.partials;
-            bp.red.counter = rs.counter;
             bp.red.cg = c.cg;
             bp.red.out = c.red_out;
+            bp.red.nvec = (op == OP_DOT) ? 2 * c.nrhs : c.nrhs;
+            bp.red.nblk = bp.nblk;
         }
         blocks += bp.nblk * c.nrhs;
     }
     B.total_blocks = blocks;
     TM_HIP(ctx, launch_blas(op, pa, pb, B, ctx->stream));
+    TM_TRY(finish_reductions(ctx, B.p, n));
     return TM_OK;
 }
 

@@ -40,7 +40,6 @@ template <int OP, int PA, int PB, int BS>
 __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 {
     __shared__ double red_sh[BS / 64];
-    __shared__ int last_sh;
 
     const int lb = blockIdx.x;
     int pi = 0;
@@ -134,16 +133,26 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                     pb.red.partials[(long)(2 * rhs) * pb.nblk + blk] = s0;
                     pb.red.partials[(long)(2 * rhs + 1) * pb.nblk + blk] = s1;
                 }
-                if (arrive_last(pb.red.counter, (unsigned)(pb.nblk * pb.nrhs), &last_sh))
-                    finish_reduce<BS>(pb.red, 2 * pb.nrhs, pb.nblk, red_sh);
             } else {
                 const double s0 = block_sum<BS>(acc0, red_sh);
                 if (threadIdx.x == 0) pb.red.partials[(long)rhs * pb.nblk + blk] = s0;
-                if (arrive_last(pb.red.counter, (unsigned)(pb.nblk * pb.nrhs), &last_sh))
-                    finish_reduce<BS>(pb.red, pb.nrhs, pb.nblk, red_sh);
             }
         }
     }
+}
+
+// One block per problem: add the partials in a fixed order, then finish.
+__global__ void __launch_bounds__(256) finish_kernel(const FinishBatch F)
+{
+    __shared__ double sh[4];
+    const Reduce &rd = F.r[blockIdx.x];
+    finish_reduce<256>(rd, rd.nvec, rd.nblk, sh);
+}
+
+hipError_t launch_finish(const FinishBatch &F, hipStream_t st)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(F.nprob), dim3(256), 0, st, F);
+    return hipGetLastError();
 }
 
 #define TM_BL(OP, PA, PB)                                                                   \

@@ -47,6 +47,7 @@ struct BlasBatch {
 };
 
 hipError_t launch_blas(int op, int pa, int pb, const BlasBatch &B, hipStream_t st);
+hipError_t launch_finish(const FinishBatch &F, hipStream_t st);
 
 // force
 hipError_t force_launch(int prec, int nf, int force_prec, void *F, void *G, const void *gauge0,

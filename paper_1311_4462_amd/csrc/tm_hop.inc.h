@@ -217,7 +217,6 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
 {
     using real = typename Prec<P>::real;
     __shared__ double red_sh[BS / 64];
-    __shared__ int last_sh;
 
     const int lb = B.xcd_remap ? xcd_logical_block(blockIdx.x, B.total_blocks) : (int)blockIdx.x;
     int pi = 0;
@@ -340,8 +339,6 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
             const double s = block_sum<BS>(nrm[r], red_sh);
             if (threadIdx.x == 0) pb.red.partials[(long)(r0 + r) * pb.nsb + sb] = s;
         }
-        if (arrive_last(pb.red.counter, (unsigned)(pb.nsb * pb.ngrp), &last_sh))
-            finish_reduce<BS>(pb.red, pb.nrhs, pb.nsb, red_sh);
     }
 }
 

@@ -477,12 +477,23 @@ struct CGScalars {
 
 enum FinOp { FIN_NONE = 0, FIN_STORE = 1, FIN_ALPHA = 2, FIN_BETA = 3, FIN_STORE_RR = 4, FIN_RELIABLE = 5 };
 
+// Two-stage deterministic reduction: every block of the producing kernel
+// stores its partial sum per vector; a separate one-block finish kernel adds
+// the partials in a fixed order and applies the finishing operation.  (No
+// atomics and no device-scope fences in the producing kernel: on a multi-XCD
+// part each such fence writes back the XCD's L2.)
 struct Reduce {
     double *partials;      // [nvec][nblk]
-    unsigned *counter;     // one per launch (reset by the last block)
     double *out;           // FIN_STORE destination [nvec]
     CGScalars *cg;         // FIN_ALPHA / FIN_BETA state [nvec]
     int op;
+    int nvec;              // filled for the finish kernel
+    int nblk;
+};
+
+struct FinishBatch {
+    int nprob;
+    Reduce r[kMaxProblems];
 };
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -507,21 +518,6 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     }
     __syncthreads();
     return s;
-}
-
-// Called by every thread of a block after thread 0 stored its partials.
-// Returns true in the block that arrives last; that block sees all partials.
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblk, int *flag_sh)
-{
-    __threadfence();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
-        *flag_sh = (prev == nblk - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = *flag_sh != 0;
-    if (last) __threadfence();
-    return last;
 }
 
 // Final reduction of partials[v][0..nblk) for v in [0, nvec) by one block,
@@ -567,7 +563,6 @@ __device__ void finish_reduce(const Reduce &rd, int nvec, int nblk, double *sh)
             }
         }
     }
-    if (threadIdx.x == 0) *rd.counter = 0u;
 }
 
 // ------------------------------------------------------------------ hop descriptors
