@@ -38,7 +38,25 @@ def site_bytes(L, S):
     return 8 * L + 2 * S, 8 * L + 3 * S
 
 
-def time_launches(torch, fn, reps):
+def measured_traffic():
+    """HBM-side bytes per launch of the roofline kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source changed since."""
+    import hashlib
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", "hop_traffic.json")))
+        csrc = os.path.join(ROOT, "paper_1311_4462_amd", "csrc")
+        src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                       for f in ("tm_hop.inc.h", "tm_impl.h", "tm_hop_fp32.hip"))
+        if hashlib.sha256(src).hexdigest()[:16] != t["source_sha256_16"]:
+            return None
+        return int(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def time_launches(torch, fn, reps, warm=3):
+    for _ in range(warm):          # first calls may run the block-size tuner
+        fn()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
@@ -69,8 +87,30 @@ def cpu_baseline(U, b_e, dims, vh, budget_s=15.0):
                       f"{'x'.join(map(str, dims))} (median {t:.2f} s each)"}
 
 
+def mat_pc_rates(torch, api, ctx, g, p, precs, reps, flops_site):
+    """Per-precision asymmetric M apply on a resident field: us, Gflop/s, algorithmic GB/s."""
+    import numpy as np
+    nf = 2 if p.flavor == api.NDEG else 1
+    vh = int(np.prod(tuple(p.dims))) // 2
+    L = {api.FP64: 96, api.FP32: 48, api.FP16: 24, api.BF16: 24}
+    S = {api.FP64: 192 * nf, api.FP32: 96 * nf, api.FP16: 52 * nf, api.BF16: 52 * nf}
+    src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
+    out = {}
+    for prec in precs:
+        x = api.tm_spinor_pack(ctx, src, p, prec, 0)
+        y = api.new_field(p, prec)
+        t = time_launches(torch, lambda: api.tm_mat_pc(ctx, y, x, g, prec, api.ASYM, 0), reps)
+        out[api.PREC_NAMES[prec]] = {"us": round(t * 1e6, 1), "gflops": round(flops_site * vh / t / 1e9, 1),
+                                     "gbs": round((16 * L[prec] + 5 * S[prec]) * vh / t / 1e9, 1)}
+        del x, y
+    del src
+    return out
+
+
 def cg_comparison(torch, api, inputs, reps=3):
-    """32^3 x 64 doublet, mu = 0.15, eps = 0.19, kappa = 0.1615: FP64 CG vs mixed CG."""
+    """32^3 x 64 doublet, mu = 0.15, eps = 0.19, kappa = 0.1615: FP64 CG vs mixed CG;
+    also the operator apply rates on this lattice (doublet in all precisions, one
+    flavour in FP32), whose working sets exceed the 256 MB last-level cache."""
     dims = (32, 32, 32, 64)
     p = api.make_params(dims, 0.1615, 0.15, 0.19, api.NDEG)
     log("cg: generating 32^3x64 links")
@@ -80,6 +120,13 @@ def cg_comparison(torch, api, inputs, reps=3):
     ctx = api.Context()
     ctx.set_tuning(True)
     g = api.Gauge(ctx, Ut, p, recon=12, precs=(api.FP64, api.FP32, api.FP16, api.BF16))
+    rates = {"nd": mat_pc_rates(torch, api, ctx, g, p, (api.FP64, api.FP32, api.FP16, api.BF16), 20,
+                                FLOPS_PER_SITE["nd"])}
+    pd = api.make_params(dims, 0.1615, 0.004, 0.0, api.PLUS)
+    gd = api.Gauge(ctx, Ut, pd, recon=12, precs=(api.FP32,))
+    rates["deg"] = mat_pc_rates(torch, api, ctx, gd, pd, (api.FP32,), 20, FLOPS_PER_SITE["deg_asym"])
+    gd.close()
+    log(f"32^3x64 mat_pc rates: {rates}")
     del Ut
     b = inputs.gaussian_spinor(dims, 2, 2003)
     tb = api.tm_spinor_pack(ctx, b[None], p, api.FP64, 0)
@@ -103,6 +150,7 @@ def cg_comparison(torch, api, inputs, reps=3):
     g.close()
     ctx.close()
     out["speedup_fp16_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_fp16"]["seconds"], 3)
+    out["mat_pc_rates"] = rates
     return out
 
 
@@ -174,7 +222,8 @@ def main():
     ach = b2 * vh / t_k2 / 1e9
     mat_bytes = (b1 + b2) * vh
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
+                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "hop_kernel<FP32, 1 flavour, 1 rhs, 12-real links> with epilogue R x + k D",
                 "bytes_per_launch": b2 * vh, "us_per_launch": round(t_k2 * 1e6, 2)}
     extra = {

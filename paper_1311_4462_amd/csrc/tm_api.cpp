@@ -1087,7 +1087,18 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     }
     const int lp = mixed ? inner : TM_FP64;
     const int xp = mixed ? TM_FP32 : TM_FP64;
-    TM_TRY(true_residual(ctx, pr, pc, lp, rv, pv, FIN_STORE_RR));
+    if (par->use_x0) {
+        TM_TRY(true_residual(ctx, pr, pc, lp, rv, pv, FIN_STORE_RR));
+    } else {
+        // x = 0: r = p = c, no operator application needed
+        BlasCall calls[kMaxProblems];
+        for (int i = 0; i < n; i++)
+            calls[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].c, nullptr, rv[i], pv[i]}, FIN_STORE_RR,
+                                pr[i].cg, pr[i].dres};
+        TM_TRY(launch_blas_batch(ctx, OP_RESIDUAL, TM_FP64, lp, nf, calls, n));
+    }
+    // true_valid: the scalars' rr is the true FP64 residual of the current x
+    bool true_valid = true;
 
     // one CG iteration over all problems, all stages batched
     auto iteration = [&]() -> int {
@@ -1150,6 +1161,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             step = m;
         }
         iters += step;
+        true_valid = false;
         TM_TRY(read_scalars(ctx, pr, sc));
         bool need_update = false, bad = false;
         for (int i = 0; i < n; i++)
@@ -1175,6 +1187,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
                 xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg, nullptr};
             TM_TRY(launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n));
             updates++;
+            true_valid = true;
             TM_TRY(read_scalars(ctx, pr, sc));
             for (int i = 0; i < n; i++)
                 for (int r = 0; r < pr[i].nrhs; r++) maxrr[i][r] = sc[i][r].rr;
@@ -1182,6 +1195,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         } else if (!mixed && converged_lo) {
             // verify with the true residual; restart from it if it is not small enough
             TM_TRY(true_residual(ctx, pr, pc, TM_FP64, rv, pv, FIN_STORE_RR));
+            true_valid = true;
             TM_TRY(read_scalars(ctx, pr, sc));
             done = all_inactive();
         }
@@ -1196,6 +1210,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             acc[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, nullptr, nullptr}, FIN_NONE,
                               nullptr, nullptr};
         TM_TRY(launch_blas_batch(ctx, OP_ACCUM_ZERO, TM_FP64, TM_FP32, nf, acc, n));
+        true_valid = false;
     }
     TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1211,8 +1226,15 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             r64[i] = workspace(ctx, name, spinor_field_bytes(TM_FP64, pr[i].g->vh, nf, pr[i].nrhs), &rc);
             if (!r64[i]) return rc;
         }
-        TM_TRY(true_residual(ctx, pr, pc, TM_FP64, r64, nullptr, FIN_NONE));
-        TM_TRY(norms_fp64(ctx, pr, r64, rn));
+        if (true_valid) {
+            // the last step computed the FP64 residual of this x (in the scalars)
+            rn.assign(n, {});
+            for (int i = 0; i < n; i++)
+                for (int r = 0; r < pr[i].nrhs; r++) rn[i].push_back(sc[i][r].rr);
+        } else {
+            TM_TRY(true_residual(ctx, pr, pc, TM_FP64, r64, nullptr, FIN_NONE));
+            TM_TRY(norms_fp64(ctx, pr, r64, rn));
+        }
         // |b - M x|: y = M x, r = b - y  (MATDAG_MAT: y = M^+ M x, left in y by the
         // residual above)
         void *ys[kMaxProblems];
@@ -1221,8 +1243,10 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             ys[i] = pr[i].y;
             xs[i] = pr[i].x;
         }
-        if (par->solution != TM_SOLUTION_MATDAG_MAT)
-            TM_TRY(mat_pc_batch(ctx, gs, ys, xs, nr, n, TM_FP64, pc, 0, FIN_NONE, nullptr));
+        if (par->solution != TM_SOLUTION_MATDAG_MAT || true_valid)
+            TM_TRY(par->solution != TM_SOLUTION_MATDAG_MAT
+                       ? mat_pc_batch(ctx, gs, ys, xs, nr, n, TM_FP64, pc, 0, FIN_NONE, nullptr)
+                       : normal_op64(ctx, pr, pc, ys, r64, xs));
         BlasCall calls[kMaxProblems];
         for (int i = 0; i < n; i++)
             calls[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].b, pr[i].y, r64[i], nullptr}, FIN_NONE,

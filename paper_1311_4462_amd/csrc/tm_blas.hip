@@ -84,9 +84,11 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
             } else if constexpr (OP == OP_RESIDUAL) {
                 cx<double> c[12], y[12];
                 load_d<PA>(c, pb.v[0], vh, vec, cb);
-                load_d<PA>(y, pb.v[1], vh, vec, cb);
+                if (pb.v[1].data) {          // y absent: r = c (zero initial guess)
+                    load_d<PA>(y, pb.v[1], vh, vec, cb);
 #pragma unroll
-                for (int k = 0; k < 12; k++) c[k] = c[k] - y[k];
+                    for (int k = 0; k < 12; k++) c[k] = c[k] - y[k];
+                }
                 // the norm is that of the FP64 residual, before any rounding
                 acc0 += nrm2_12(c);
                 store_d<PB>(pb.v[2], vh, vec, cb, c);
