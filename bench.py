@@ -154,6 +154,100 @@ def cg_comparison(torch, api, inputs, reps=3):
     return out
 
 
+def batched_section(torch, api, inputs):
+    """Many sources and uneven lattices: 16 Z2 sources on 24^3 x 48 in one solve
+    versus 16 single solves, and four lattices (8^4, 12^3x24, 16^3x32, 20^3x40,
+    4 sources each) in one graph-captured solve versus eager launches and
+    separate solves.  Mixed precision (FP16 storage) to a 1e-10 FP64 residual."""
+    import numpy as np
+    out = {}
+    ctx = api.Context()
+    ctx.set_tuning(True)
+    dims = (24, 24, 24, 48)
+    p = api.make_params(dims, 0.1615, 0.004, 0.0, api.PLUS)
+    U = torch.from_numpy(inputs.gauge_field(dims, "near_unit", 1004)).cuda()
+    g = api.Gauge(ctx, U, p, recon=12, precs=(api.FP64, api.FP16))
+    del U
+    z = torch.from_numpy(inputs.z2_spinor(dims, 1, 2004, nrhs=16)).cuda()
+    b16 = api.tm_spinor_pack(ctx, z, p, api.FP64, 0, 16)
+    bs = [api.tm_spinor_pack(ctx, z[r:r + 1], p, api.FP64, 0, 1) for r in range(16)]
+    del z
+    for name, inner in (("fp64", api.FP64), ("mixed_fp16", api.FP16)):
+        x = api.new_field(p, api.FP64, 16)
+        api.tm_cg(ctx, x, b16, g, tol=1e-10, inner=inner, nrhs=16)      # warm (tuner)
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        r16 = api.tm_cg(ctx, x, b16, g, tol=1e-10, inner=inner, nrhs=16)
+        torch.cuda.synchronize(); t_batch = time.perf_counter() - t0
+        x1 = api.new_field(p, api.FP64)
+        api.tm_cg(ctx, x1, bs[0], g, tol=1e-10, inner=inner)
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        its = []
+        for r in range(16):
+            its.append(api.tm_cg(ctx, x1, bs[r], g, tol=1e-10, inner=inner)[0]["iters"])
+        torch.cuda.synchronize(); t_seq = time.perf_counter() - t0
+        out[f"sources16_24x24x24x48_{name}"] = {
+            "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
+            "speedup": round(t_seq / t_batch, 3), "batched_iters": r16[0]["iters"],
+            "max_res": max(r["true_rel_res_normal"] for r in r16), "sequential_iters_mean": float(np.mean(its))}
+        log(f"batched {name}: {out[f'sources16_24x24x24x48_{name}']}")
+    g.close()
+    # uneven lattices
+    dl = [(8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32), (20, 20, 20, 40)]
+    gs, xs, bb = [], [], []
+    for i, d in enumerate(dl):
+        pp = api.make_params(d, 0.1615, 0.004, 0.0, api.PLUS)
+        Ui = torch.from_numpy(inputs.gauge_field(d, "near_unit", 1040 + i)).cuda()
+        gs.append(api.Gauge(ctx, Ui, pp, recon=12, precs=(api.FP64, api.FP16)))
+        zi = torch.from_numpy(inputs.z2_spinor(d, 1, 2040 + i, nrhs=4)).cuda()
+        bb.append(api.tm_spinor_pack(ctx, zi, pp, api.FP64, 0, 4))
+        xs.append(api.new_field(pp, api.FP64, 4))
+    res = {}
+    for name, kw in (("graph8", dict(graph_iters=8)), ("eager", dict(check_every=8))):
+        api.tm_cg_batched(ctx, gs, xs, bb, [4] * 4, tol=1e-10, inner=api.FP16, **kw)   # warm
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        rr = api.tm_cg_batched(ctx, gs, xs, bb, [4] * 4, tol=1e-10, inner=api.FP16, **kw)
+        torch.cuda.synchronize()
+        res[name] = {"s": round(time.perf_counter() - t0, 4), "iters": rr[0]["iters"],
+                     "max_res": max(r["true_rel_res_normal"] for r in rr)}
+    torch.cuda.synchronize(); t0 = time.perf_counter()
+    for i in range(4):
+        api.tm_cg(ctx, xs[i], bb[i], gs[i], tol=1e-10, inner=api.FP16, nrhs=4)
+    torch.cuda.synchronize()
+    res["separate_solves_s"] = round(time.perf_counter() - t0, 4)
+    out["uneven_lattices_4x4_sources"] = res
+    log(f"uneven lattices: {res}")
+    for gg in gs:
+        gg.close()
+    ctx.close()
+    return out
+
+
+def force_section(torch, api, inputs):
+    """16^3 x 32 doublet: FP32 force kernel time and bytes, and one autograd step
+    (FP64 solve recomputed in backward + force)."""
+    from paper_1311_4462_amd.autograd import tm_action
+    dims = (16, 16, 16, 32)
+    p = api.make_params(dims, 0.1615, 0.15, 0.19, api.NDEG)
+    U = torch.from_numpy(inputs.gauge_field(dims, "near_unit", 1005)).cuda()
+    phi = torch.from_numpy(inputs.gaussian_spinor(dims, 2, 2005)).cuda()
+    ctx = api.Context()
+    g = api.Gauge(ctx, U, p, recon=12, precs=(api.FP64, api.FP32))
+    xb = api.tm_spinor_pack(ctx, phi[None], p, api.FP32, 0)
+    F = torch.empty(U.shape, dtype=torch.complex64, device="cuda")
+    t = time_launches(torch, lambda: api.tm_force(ctx, F, api.FP32, xb, g, api.FP32, api.ASYM, 1.0, False, None), 20)
+    vh = (dims[0] * dims[1] * dims[2] * dims[3]) // 2
+    Ur = U.clone().requires_grad_(True)
+    torch.cuda.synchronize(); t0 = time.perf_counter()
+    S = tm_action(Ur, phi, p)
+    S.backward()
+    torch.cuda.synchronize(); t_ag = time.perf_counter() - t0
+    g.close(); ctx.close()
+    return {"force_16x16x16x32_nd": {"tm_force_fp32_us": round(t * 1e6, 1),
+                                      "note": "tm_force = M X, two hops for Z and W, and the outer-product kernel",
+                                      "autograd_forward_backward_s": round(t_ag, 4),
+                                      "links": 4 * 2 * vh}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +257,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cg-only", action="store_true", help="only the CG comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched / force sections")
     ap.add_argument("--cg-reps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
@@ -265,6 +360,9 @@ def main():
         del Uc
     if not a.no_cg:
         extra["cg_32x32x32x64_nd"] = cg_comparison(torch, api, inputs, a.cg_reps)
+    if not a.no_batch:
+        extra["batched"] = batched_section(torch, api, inputs)
+        extra.update(force_section(torch, api, inputs))
 
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gflop/s", "n_gpus": 1,

@@ -209,7 +209,7 @@ def _results(res, n):
                  true_rel_res_pc=res[i].true_rel_res_pc, seconds=res[i].seconds) for i in range(n)]
 
 
-def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64, delta=0.1,
+def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64, delta=0.0,
           use_x0=False, nrhs=1, graph_iters=0, check_every=1, solution=SOLUTION_MAT):
     """CG on the normal equations of the preconditioned operator; x_e, b_e FP64 native."""
     p = _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every, solution)
@@ -222,7 +222,7 @@ def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=F
 
 
 def tm_cg_batched(ctx, gauges, xs, bs, nrhs, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64,
-                  delta=0.1, graph_iters=0, check_every=1, solution=SOLUTION_MAT):
+                  delta=0.0, graph_iters=0, check_every=1, solution=SOLUTION_MAT):
     n = len(gauges)
     p = _cg_params(pc, tol, maxiter, inner, delta, False, nrhs[0], graph_iters, check_every, solution)
     ga = (ctypes.c_void_p * n)(*[g.h.value for g in gauges])

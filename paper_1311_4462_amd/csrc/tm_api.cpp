@@ -997,7 +997,10 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     const int pc = par->pc;
     const int inner = par->inner;
     const bool mixed = inner != TM_FP64;
-    const double delta = par->delta > 0 ? par->delta : 0.1;
+    // reliable-update threshold: by default 0.01 for half-precision inner
+    // iterations and 0.001 for FP32 (the residual is replaced once it has
+    // dropped by 1/delta since the last replacement)
+    const double delta = par->delta > 0 ? par->delta : (inner == TM_FP32 ? 1e-3 : 1e-2);
     const int check_every = std::max(1, par->check_every);
     const int nf = pr[0].g->nf;
 

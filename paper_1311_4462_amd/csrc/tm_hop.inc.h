@@ -170,10 +170,15 @@ __device__ __forceinline__ void hop_direction(cx<typename Prec<P>::real> (&acc)[
 #ifndef TM_HOP_WAVES_LIGHT
 #define TM_HOP_WAVES_LIGHT 4
 #endif
+#ifndef TM_HOP_WAVES_ND
+#define TM_HOP_WAVES_ND 2
+#endif
 template <int P, int NF, int NR>
 constexpr int hop_waves()
 {
-    return (P == TM_FP64 && NF * NR == 1) ? 3 : (P == TM_FP64 || NF * NR > 1) ? 2 : TM_HOP_WAVES_LIGHT;
+    return (P == TM_FP64 && NF * NR == 1) ? 3
+           : (P != TM_FP64 && NF == 2 && NR == 1) ? TM_HOP_WAVES_ND
+           : (P == TM_FP64 || NF * NR > 1) ? 2 : TM_HOP_WAVES_LIGHT;
 }
 
 // Keeps the compiler from hoisting the loads of all eight hops ahead of the
