@@ -300,7 +300,8 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
         hp.vh = (int)g->vh;
         hp.nrhs = c.nrhs;
         hp.blk_start = blocks;
-        hp.nsb = (int)((g->vh + bs - 1) / bs);
+        const int spb = (nf == 2 && kNdSplit) ? bs / 2 : bs;      // sites per block
+        hp.nsb = (int)((g->vh + spb - 1) / spb);
         hp.ngrp = c.nrhs / nr;
         hp.out_parity = c.out_parity;
         hp.tsign = g->p.t_antiperiodic ? -1.0 : 1.0;

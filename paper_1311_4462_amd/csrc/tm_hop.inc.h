@@ -117,18 +117,85 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
     }
 }
 
+// Doublet sites are split over lane pairs: lane 2k holds flavour 0 and lane
+// 2k+1 flavour 1 of the same site (both load the same link, which the memory
+// pipeline coalesces into one request); the flavour-mixing twist exchanges
+// the partner's values with a lane-xor-1 shuffle.  This keeps the per-thread
+// state of the doublet kernel at that of the one-flavour kernel.
+template <int NF>
+constexpr bool nd_split()
+{
+    return NF == 2 && kNdSplit;
+}
+template <int NF>
+constexpr int flavours_per_thread()
+{
+    return nd_split<NF>() ? 1 : NF;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> partner(cx<T> a)
+{
+    return mk(__shfl_xor(a.re, 1, 64), __shfl_xor(a.im, 1, 64));
+}
+
+// This lane's flavour of R v or R^-1 v for a split doublet (the other
+// flavour's v comes from the partner lane):
+//   (R v)_f = v_f + i ta t3_f g5 v_f + b v_(1-f),
+//   (R^-1 v)_f = c (v_f - i ta t3_f g5 v_f - b v_(1-f)).
+template <typename T>
+__device__ __forceinline__ void twist_split(cx<T> (&o)[12], const cx<T> (&v)[12], const Twist &tw,
+                                            bool inverse, int fl)
+{
+    const T s = inverse ? (T)-1 : (T)1;
+    const T c = inverse ? (T)tw.c : (T)1;
+    const T t3 = fl ? (T)-tw.ta : (T)tw.ta;
+    const T b = (T)tw.b;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const int kk = (k < 6) ? k + 6 : k - 6;
+        const cx<T> r = v[k] + (s * t3) * times_i(v[kk]) + (s * b) * partner(v[k]);
+        o[k] = c * r;
+    }
+}
+
 // One direction, forward (FWD) or backward, for all rhs and flavours.
 template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int MU, bool FWD>
-__device__ __forceinline__ void hop_direction(cx<typename Prec<P>::real> (&acc)[NR][NF][12],
-                                              const HopProblem &pb, uint32_t nb, uint32_t link_cb,
-                                              int link_par, int r0, typename Prec<P>::real sgn)
+__device__ __forceinline__ void hop_direction(
+    cx<typename Prec<P>::real> (&acc)[NR][flavours_per_thread<NF>()][12], const HopProblem &pb,
+    uint32_t nb, uint32_t link_cb, int link_par, int r0, typename Prec<P>::real sgn, int fl)
 {
     using real = typename Prec<P>::real;
     constexpr int SIG = (FWD != DAG) ? 1 : -1;   // D: 1 - g forward; D^+ swaps
     const uint32_t vh = pb.vh;
     cx<real> u[3][3];
     LinkIO<P, RECON, LNT>::load(u, pb.gauge[link_par], vh, MU, link_cb);
-    if constexpr (TWL) {
+    if constexpr (nd_split<NF>()) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<real> v[12];
+            const uint32_t vec = (uint32_t)((r0 + r) * NF + fl);
+            if constexpr (TWL) {
+                cx<real> w[12];
+                SpinorIO<P>::template load<0, 12>(w, pb.in, vh, vec, nb);
+                twist_split(v, w, pb.tw, true, fl);
+                if constexpr (MU == 3)
+                    hop_accumulate<MU, SIG, !FWD>(acc[r][0], u, v + (SIG > 0 ? 6 : 0), sgn);
+                else
+                    hop_accumulate<MU, SIG, !FWD>(acc[r][0], u, v, sgn);
+            } else {
+                if constexpr (MU == 3) {
+                    if constexpr (SIG > 0)
+                        SpinorIO<P>::template load<6, 6>(v, pb.in, vh, vec, nb);
+                    else
+                        SpinorIO<P>::template load<0, 6>(v, pb.in, vh, vec, nb);
+                } else {
+                    SpinorIO<P>::template load<0, 12>(v, pb.in, vh, vec, nb);
+                }
+                hop_accumulate<MU, SIG, !FWD>(acc[r][0], u, v, sgn);
+            }
+        }
+    } else if constexpr (TWL) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             cx<real> v[NF][12];
@@ -176,22 +243,23 @@ __device__ __forceinline__ void hop_direction(cx<typename Prec<P>::real> (&acc)[
 template <int P, int NF, int NR>
 constexpr int hop_waves()
 {
-    return (P == TM_FP64 && NF * NR == 1) ? 3
-           : (P != TM_FP64 && NF == 2 && NR == 1) ? TM_HOP_WAVES_ND
-           : (P == TM_FP64 || NF * NR > 1) ? 2 : TM_HOP_WAVES_LIGHT;
+    constexpr int NFT = flavours_per_thread<NF>();
+    return (P == TM_FP64 && NFT * NR == 1) ? 3
+           : (P != TM_FP64 && NFT == 2 && NR == 1) ? TM_HOP_WAVES_ND
+           : (P == TM_FP64 || NFT * NR > 1) ? 2 : TM_HOP_WAVES_LIGHT;
 }
 
 // Keeps the compiler from hoisting the loads of all eight hops ahead of the
 // arithmetic, which needs far more registers than the occupancy target
 // allows: the accumulators are pinned to registers at this point and no
 // memory access moves across it.
-template <typename T, int NR, int NF>
-__device__ __forceinline__ void dir_fence(cx<T> (&acc)[NR][NF][12])
+template <typename T, int NR, int NFT>
+__device__ __forceinline__ void dir_fence(cx<T> (&acc)[NR][NFT][12])
 {
 #pragma unroll
     for (int r = 0; r < NR; r++)
 #pragma unroll
-        for (int f = 0; f < NF; f++)
+        for (int f = 0; f < NFT; f++)
 #pragma unroll
             for (int k = 0; k < 12; k++)
                 __asm__ volatile("" : "+v"(acc[r][f][k].re), "+v"(acc[r][f][k].im)::"memory");
@@ -205,7 +273,7 @@ constexpr int fence_mode()
 #ifdef TM_FENCE_MODE
     return TM_FENCE_MODE;
 #else
-    return (P == TM_FP64 || NF * NR > 1) ? 2 : 1;
+    return (P == TM_FP64 || flavours_per_thread<NF>() * NR > 1) ? 2 : 1;
 #endif
 }
 #define TM_DIR_FENCE()                                   \
@@ -229,11 +297,15 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
         if (lb >= B.p[i].blk_start) pi = i;
     const HopProblem &pb = B.p[pi];
 
+    constexpr bool SPLIT = nd_split<NF>();
+    constexpr int NFT = flavours_per_thread<NF>();
+    constexpr int SPB = SPLIT ? BS / 2 : BS;          // sites per block
     const int lbl = lb - pb.blk_start;
     const int sb = lbl / pb.ngrp;
     const int grp = lbl - sb * pb.ngrp;
     const int r0 = grp * NR;
-    const uint32_t cb = (uint32_t)sb * BS + threadIdx.x;
+    const int fl = SPLIT ? (int)(threadIdx.x & 1) : 0;  // this lane's flavour (split doublet)
+    const uint32_t cb = (uint32_t)sb * SPB + (SPLIT ? threadIdx.x >> 1 : threadIdx.x);
     const uint32_t vh = pb.vh;
     const bool valid = cb < vh;
 
@@ -256,11 +328,11 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
         const uint32_t sy = xh_n, sz = (uint32_t)xh_n * Ly, st = (uint32_t)xh_n * Ly * Lz;
         const int npar = 1 - par;
 
-        cx<real> acc[NR][NF][12];
+        cx<real> acc[NR][NFT][12];
 #pragma unroll
         for (int r = 0; r < NR; r++)
 #pragma unroll
-            for (int f = 0; f < NF; f++)
+            for (int f = 0; f < NFT; f++)
 #pragma unroll
                 for (int k = 0; k < 12; k++) acc[r][f][k] = mk((real)0, (real)0);
 
@@ -270,27 +342,27 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
             const int xp = (x + 1 == Lx) ? 0 : x + 1;
             const int xm = (x == 0) ? Lx - 1 : x - 1;
             const uint32_t nf_ = base + (xp >> 1), nb_ = base + (xm >> 1);
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, true>(acc, pb, nf_, cb, par, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, true>(acc, pb, nf_, cb, par, r0, one, fl);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, false>(acc, pb, nb_, nb_, npar, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, false>(acc, pb, nb_, nb_, npar, r0, one, fl);
             TM_DIR_FENCE();
         }
         // y direction
         {
             const uint32_t nf_ = (y == Ly - 1) ? cb - (uint32_t)(Ly - 1) * sy : cb + sy;
             const uint32_t nb_ = (y == 0) ? cb + (uint32_t)(Ly - 1) * sy : cb - sy;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, true>(acc, pb, nf_, cb, par, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, true>(acc, pb, nf_, cb, par, r0, one, fl);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, false>(acc, pb, nb_, nb_, npar, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, false>(acc, pb, nb_, nb_, npar, r0, one, fl);
             TM_DIR_FENCE();
         }
         // z direction
         {
             const uint32_t nf_ = (z == Lz - 1) ? cb - (uint32_t)(Lz - 1) * sz : cb + sz;
             const uint32_t nb_ = (z == 0) ? cb + (uint32_t)(Lz - 1) * sz : cb - sz;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, true>(acc, pb, nf_, cb, par, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, true>(acc, pb, nf_, cb, par, r0, one, fl);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, false>(acc, pb, nb_, nb_, npar, r0, one);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, false>(acc, pb, nb_, nb_, npar, r0, one, fl);
             TM_DIR_FENCE();
         }
         // t direction (boundary factor on hops across t = Lt-1 <-> 0)
@@ -299,40 +371,77 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
             const uint32_t nb_ = (t == 0) ? cb + (uint32_t)(Lt - 1) * st : cb - st;
             const real sf = (t == Lt - 1) ? (real)pb.tsign : one;
             const real sbk = (t == 0) ? (real)pb.tsign : one;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, true>(acc, pb, nf_, cb, par, r0, sf);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, true>(acc, pb, nf_, cb, par, r0, sf, fl);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, false>(acc, pb, nb_, nb_, npar, r0, sbk);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, false>(acc, pb, nb_, nb_, npar, r0, sbk, fl);
             TM_DIR_FENCE();
         }
 
         // epilogue
         const real kk = (real)pb.k;
+        const int epi = B.epi;
+        if constexpr (SPLIT) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            cx<real> (&A)[NF][12] = acc[r];
-            const int epi = B.epi;
-            if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) apply_twist<real, NF>(A, pb.tw, true);
-            if (epi >= TM_EPI_RX_PLUS_KD) {
-                cx<real> X[NF][12];
+            for (int r = 0; r < NR; r++) {
+                cx<real> (&A)[12] = acc[r][0];
+                cx<real> T[12];
+                if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) {
+                    twist_split(T, A, pb.tw, true, fl);
 #pragma unroll
-                for (int f = 0; f < NF; f++)
-                    SpinorIO<P>::template load<0, 12>(X[f], pb.x, vh, (uint32_t)((r0 + r) * NF + f), cb);
-                if (epi == TM_EPI_RX_PLUS_KD) apply_twist<real, NF>(X, pb.tw, false);
+                    for (int k = 0; k < 12; k++) A[k] = T[k];
+                }
+                if (epi >= TM_EPI_RX_PLUS_KD) {
+                    cx<real> X[12];
+                    SpinorIO<P>::template load<0, 12>(X, pb.x, vh, (uint32_t)((r0 + r) * NF + fl), cb);
+                    if (epi == TM_EPI_RX_PLUS_KD) {
+                        twist_split(T, X, pb.tw, false, fl);
 #pragma unroll
-                for (int f = 0; f < NF; f++)
+                        for (int k = 0; k < 12; k++) X[k] = T[k];
+                    }
 #pragma unroll
-                    for (int k = 0; k < 12; k++) A[f][k] = X[f][k] + kk * A[f][k];
-                if (epi == TM_EPI_TWINV_X_PLUS_KD) apply_twist<real, NF>(A, pb.tw, true);
-            }
+                    for (int k = 0; k < 12; k++) A[k] = X[k] + kk * A[k];
+                    if (epi == TM_EPI_TWINV_X_PLUS_KD) {
+                        twist_split(T, A, pb.tw, true, fl);
 #pragma unroll
-            for (int f = 0; f < NF; f++) {
-                SpinorIO<P>::store(pb.out, vh, (uint32_t)((r0 + r) * NF + f), cb, A[f]);
+                        for (int k = 0; k < 12; k++) A[k] = T[k];
+                    }
+                }
+                SpinorIO<P>::store(pb.out, vh, (uint32_t)((r0 + r) * NF + fl), cb, A);
                 if (pb.red.op != FIN_NONE) {
                     double s = 0.0;
 #pragma unroll
                     for (int k = 0; k < 12; k++)
-                        s += (double)A[f][k].re * A[f][k].re + (double)A[f][k].im * A[f][k].im;
+                        s += (double)A[k].re * A[k].re + (double)A[k].im * A[k].im;
                     nrm[r] += s;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                cx<real> (&A)[NFT][12] = acc[r];
+                if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) apply_twist<real, NF>(A, pb.tw, true);
+                if (epi >= TM_EPI_RX_PLUS_KD) {
+                    cx<real> X[NF][12];
+#pragma unroll
+                    for (int f = 0; f < NF; f++)
+                        SpinorIO<P>::template load<0, 12>(X[f], pb.x, vh, (uint32_t)((r0 + r) * NF + f), cb);
+                    if (epi == TM_EPI_RX_PLUS_KD) apply_twist<real, NF>(X, pb.tw, false);
+#pragma unroll
+                    for (int f = 0; f < NF; f++)
+#pragma unroll
+                        for (int k = 0; k < 12; k++) A[f][k] = X[f][k] + kk * A[f][k];
+                    if (epi == TM_EPI_TWINV_X_PLUS_KD) apply_twist<real, NF>(A, pb.tw, true);
+                }
+#pragma unroll
+                for (int f = 0; f < NF; f++) {
+                    SpinorIO<P>::store(pb.out, vh, (uint32_t)((r0 + r) * NF + f), cb, A[f]);
+                    if (pb.red.op != FIN_NONE) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int k = 0; k < 12; k++)
+                            s += (double)A[f][k].re * A[f][k].re + (double)A[f][k].im * A[f][k].im;
+                        nrm[r] += s;
+                    }
                 }
             }
         }

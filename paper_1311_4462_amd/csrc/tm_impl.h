@@ -11,6 +11,12 @@
 namespace twm {
 
 constexpr int kMaxProblems = 8;   // problems per batched launch
+
+// Doublet hop kernels put the two flavours of a site on a lane pair.
+#ifndef TM_ND_SPLIT
+#define TM_ND_SPLIT 1
+#endif
+constexpr bool kNdSplit = TM_ND_SPLIT != 0;
 constexpr int kBlock = 256;       // default threads per block
 
 // ------------------------------------------------------------------ complex
