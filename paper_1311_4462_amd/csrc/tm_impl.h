@@ -12,9 +12,11 @@ namespace twm {
 
 constexpr int kMaxProblems = 8;   // problems per batched launch
 
-// Doublet hop kernels put the two flavours of a site on a lane pair.
+// Doublet hop kernels can put the two flavours of a site on a lane pair
+// (build with TM_ND_SPLIT=1); measured 2-4% slower than one thread per site,
+// so off by default.
 #ifndef TM_ND_SPLIT
-#define TM_ND_SPLIT 1
+#define TM_ND_SPLIT 0
 #endif
 constexpr bool kNdSplit = TM_ND_SPLIT != 0;
 constexpr int kBlock = 256;       // default threads per block
