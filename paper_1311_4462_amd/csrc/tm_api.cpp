@@ -36,6 +36,7 @@ struct tm_ctx {
     std::map<std::string, int> tuned;  // kernel key -> block size
     int force_bs = 0;                  // TM_HOP_BS: fixed block size (0: tuned / default)
     int force_lnt = -1;                // TM_LINK_NT: 1 / 0 fixes the link load policy
+    const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
 };
 
@@ -288,6 +289,7 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
     const int prec = calls[0].prec, nf = calls[0].g->nf;
     memset(B, 0, sizeof(*B));
     B->nprob = n;
+    B->gate = ctx->gate;
     B->epi = calls[0].epi;
     B->xcd_remap = ctx->xcd_remap;
     int blocks = 0;
@@ -345,6 +347,7 @@ int finish_reductions(tm_ctx *ctx, const Prob *p, int n)
     }
     if (!any) return TM_OK;
     F.nprob = n;
+    F.gate = ctx->gate;
     TM_HIP(ctx, launch_finish(F, ctx->stream));
     return TM_OK;
 }
@@ -436,6 +439,7 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
     memset(&B, 0, sizeof(B));
     B.nprob = n;
     B.nf = nf;
+    B.gate = ctx->gate;
     int blocks = 0;
     for (int i = 0; i < n; i++) {
         const BlasCall &c = calls[i];
@@ -842,7 +846,7 @@ struct CGProblem {
     void *x;            // FP64 solution (user)
     const void *b;      // FP64 rhs (user)
     // FP64 work vectors
-    void *c, *y, *r64, *p64, *mp64, *ap64;
+    void *c, *y, *mid, *r64, *p64, *mp64, *ap64;
     // low-precision work vectors (mixed)
     void *rlo, *plo, *mplo, *aplo, *xlo;
     CGScalars *cg;      // device [nrhs]
@@ -862,7 +866,8 @@ int cg_setup_vectors(tm_ctx *ctx, CGProblem &pr, int slot, int inner)
     };
     pr.c = vec("c", b64);
     pr.y = vec("y", b64);
-    if (!pr.c || !pr.y) return rc;
+    pr.mid = vec("mid", b64);
+    if (!pr.c || !pr.y || !pr.mid) return rc;
     if (inner == TM_FP64) {
         pr.r64 = vec("r", b64);
         pr.p64 = vec("p", b64);
@@ -966,11 +971,7 @@ int true_residual(tm_ctx *ctx, std::vector<CGProblem> &pr, int pc, int rp, void 
     for (int i = 0; i < n; i++) {
         ys[i] = pr[i].y;
         xs[i] = pr[i].x;
-        int rc = TM_OK;
-        char name[64];
-        snprintf(name, sizeof(name), "cg_mid_%d", i);
-        mids[i] = workspace(ctx, name, spinor_field_bytes(TM_FP64, pr[i].g->vh, pr[i].g->nf, pr[i].nrhs), &rc);
-        if (!mids[i]) return rc;
+        mids[i] = pr[i].mid;
     }
     TM_TRY(normal_op64(ctx, pr, pc, ys, mids, xs));
     BlasCall calls[kMaxProblems];
@@ -1104,20 +1105,63 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     // true_valid: the scalars' rr is the true FP64 residual of the current x
     bool true_valid = true;
 
-    // one CG iteration over all problems, all stages batched
-    auto iteration = [&]() -> int {
+    // One CG iteration over all problems, every stage one batched launch:
+    // M p (|M p|^2 -> alpha), M^+ M p, x += alpha p / r -= alpha A p (|r|^2 -> beta).
+    auto iteration_core = [&]() -> int {
         CGScalars *cgs[kMaxProblems];
         for (int i = 0; i < n; i++) cgs[i] = pr[i].cg;
         TM_TRY(mat_pc_batch(ctx, gs, mpv, (const void *const *)pv, nr, n, lp, pc, 0, FIN_ALPHA, cgs));
         TM_TRY(mat_pc_batch(ctx, gs, apv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_NONE, nullptr));
-        BlasCall up[kMaxProblems], xp_[kMaxProblems];
-        for (int i = 0; i < n; i++) {
+        BlasCall up[kMaxProblems];
+        for (int i = 0; i < n; i++)
             up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], rv[i], apv[i]}, FIN_BETA, pr[i].cg, nullptr};
+        return launch_blas_batch(ctx, OP_CG_UPDATE, xp, lp, nf, up, n);
+    };
+    // p = r + beta p (beta of the CG recurrence, or of a residual replacement)
+    auto xpay = [&]() -> int {
+        BlasCall xp_[kMaxProblems];
+        for (int i = 0; i < n; i++)
             xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg, nullptr};
+        return launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n);
+    };
+    // reliable update: x += x_lo; r = c - A x in FP64 rounded into r_lo; beta = |r|^2 / |r_prev|^2
+    auto reliable_update = [&]() -> int {
+        BlasCall acc[kMaxProblems];
+        for (int i = 0; i < n; i++)
+            acc[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, nullptr, nullptr}, FIN_NONE,
+                              nullptr, nullptr};
+        TM_TRY(launch_blas_batch(ctx, OP_ACCUM_ZERO, TM_FP64, TM_FP32, nf, acc, n));
+        return true_residual(ctx, pr, pc, lp, rv, nullptr, FIN_RELIABLE);
+    };
+
+    // Mixed precision with captured iterations: the reliable update is decided
+    // on the device every iteration and its launches are gated by that flag.
+    int *gate = nullptr;
+    const bool device_updates = mixed && par->graph_iters > 0;
+    if (device_updates) {
+        int rc = TM_OK;
+        gate = (int *)workspace(ctx, "cg_gate", 256, &rc);
+        if (!gate) return rc;
+        TM_HIP(ctx, hipMemsetAsync(gate, 0, 256, ctx->stream));
+    }
+    auto iteration_device_updates = [&]() -> int {
+        TM_TRY(iteration_core());
+        DecideArgs D;
+        memset(&D, 0, sizeof(D));
+        D.nprob = n;
+        for (int i = 0; i < n; i++) {
+            D.nrhs[i] = pr[i].nrhs;
+            D.cg[i] = pr[i].cg;
         }
-        TM_TRY(launch_blas_batch(ctx, OP_CG_UPDATE, xp, lp, nf, up, n));
-        TM_TRY(launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n));
-        return TM_OK;
+        D.delta2 = delta * delta;
+        D.gate = gate;
+        D.count = gate + 1;
+        TM_HIP(ctx, launch_decide(D, ctx->stream));
+        ctx->gate = gate;
+        const int rc = reliable_update();
+        ctx->gate = nullptr;
+        TM_TRY(rc);
+        return xpay();
     };
 
     GraphCache gc;
@@ -1125,7 +1169,15 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     if (gk > 0) {
         TM_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
         int rc = TM_OK;
-        for (int k = 0; k < gk && rc == TM_OK; k++) rc = iteration();
+        for (int k = 0; k < gk && rc == TM_OK; k++) {
+            if (device_updates) {
+                rc = iteration_device_updates();
+            } else {
+                rc = iteration_core();
+                if (rc == TM_OK) rc = xpay();
+            }
+        }
+        ctx->gate = nullptr;
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
         if (rc != TM_OK) {
@@ -1139,18 +1191,13 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
 
     int iters = 0, updates = 0;
     std::vector<std::vector<CGScalars>> sc;
-    std::vector<std::vector<double>> maxrr(n);
     TM_TRY(read_scalars(ctx, pr, sc));
-    for (int i = 0; i < n; i++) {
-        maxrr[i].resize(pr[i].nrhs);
-        for (int r = 0; r < pr[i].nrhs; r++) maxrr[i][r] = sc[i][r].rr;
-    }
     bool done = false;
     int status = TM_OK;
     auto all_inactive = [&]() {
         for (int i = 0; i < n; i++)
             for (int r = 0; r < pr[i].nrhs; r++)
-                if (sc[i][r].active) return false;
+                if (sc[i][r].active || (device_updates && sc[i][r].pending)) return false;
         return true;
     };
     done = all_inactive();
@@ -1159,9 +1206,15 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         if (gk > 0) {
             TM_HIP(ctx, hipGraphLaunch(gc.exec, ctx->stream));
             step = gk;
+        } else if (mixed) {
+            TM_TRY(iteration_core());
+            step = 1;
         } else {
-            const int m = mixed ? 1 : check_every;
-            for (int k = 0; k < m; k++) TM_TRY(iteration());
+            const int m = check_every;
+            for (int k = 0; k < m; k++) {
+                TM_TRY(iteration_core());
+                TM_TRY(xpay());
+            }
             step = m;
         }
         iters += step;
@@ -1172,31 +1225,23 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             for (int r = 0; r < pr[i].nrhs; r++) {
                 const CGScalars &s = sc[i][r];
                 if (!std::isfinite(s.rr) || !std::isfinite(s.alpha)) bad = true;
-                maxrr[i][r] = std::max(maxrr[i][r], s.rr);
-                if (mixed && s.active && s.rr < delta * delta * maxrr[i][r]) need_update = true;
+                if (s.pending || (s.active && s.rr < delta * delta * s.maxrr)) need_update = true;
             }
         if (bad) return fail(ctx, TM_ERR_NAN, "non-finite residual after %d iterations", iters);
-        const bool converged_lo = all_inactive();
-        if (mixed && (need_update || converged_lo)) {
-            // reliable update: x += x_lo; r = c - A x in FP64, rounded into r_lo
-            BlasCall acc[kMaxProblems];
-            for (int i = 0; i < n; i++)
-                acc[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, nullptr, nullptr}, FIN_NONE,
-                                  nullptr, nullptr};
-            TM_TRY(launch_blas_batch(ctx, OP_ACCUM_ZERO, TM_FP64, TM_FP32, nf, acc, n));
-            TM_TRY(true_residual(ctx, pr, pc, lp, rv, nullptr, FIN_RELIABLE));
-            // p = r + beta p with beta = |r_true|^2 / |r_prev|^2
-            BlasCall xp_[kMaxProblems];
-            for (int i = 0; i < n; i++)
-                xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg, nullptr};
-            TM_TRY(launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n));
-            updates++;
-            true_valid = true;
-            TM_TRY(read_scalars(ctx, pr, sc));
-            for (int i = 0; i < n; i++)
-                for (int r = 0; r < pr[i].nrhs; r++) maxrr[i][r] = sc[i][r].rr;
+        if (device_updates) {
             done = all_inactive();
-        } else if (!mixed && converged_lo) {
+        } else if (mixed) {
+            if (need_update) {
+                TM_TRY(reliable_update());
+                updates++;
+            }
+            TM_TRY(xpay());
+            if (need_update) {
+                true_valid = true;
+                TM_TRY(read_scalars(ctx, pr, sc));
+                done = all_inactive();
+            }
+        } else if (all_inactive()) {
             // verify with the true residual; restart from it if it is not small enough
             TM_TRY(true_residual(ctx, pr, pc, TM_FP64, rv, pv, FIN_STORE_RR));
             true_valid = true;
@@ -1207,6 +1252,14 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             status = TM_NOT_CONVERGED;
             break;
         }
+    }
+    if (device_updates) {
+        // updates decided on the device; the last one left x and rr consistent
+        int h[2] = {0, 0};
+        TM_HIP(ctx, hipMemcpyAsync(h, gate, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+        TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        updates = h[1];
+        true_valid = (status == TM_OK);
     }
     if (mixed && status == TM_NOT_CONVERGED) {
         BlasCall acc[kMaxProblems];

@@ -40,6 +40,7 @@ template <int OP, int PA, int PB, int BS>
 __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 {
     __shared__ double red_sh[BS / 64];
+    if (B.gate && *B.gate == 0) return;   // gated launch not needed this iteration
 
     const int lb = blockIdx.x;
     int pi = 0;
@@ -147,8 +148,28 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 __global__ void __launch_bounds__(256) finish_kernel(const FinishBatch F)
 {
     __shared__ double sh[4];
+    if (F.gate && *F.gate == 0) return;
     const Reduce &rd = F.r[blockIdx.x];
     finish_reduce<256>(rd, rd.nvec, rd.nblk, sh);
+}
+
+__global__ void decide_kernel(const DecideArgs D)
+{
+    if (threadIdx.x != 0) return;
+    int need = 0;
+    for (int i = 0; i < D.nprob; i++)
+        for (int r = 0; r < D.nrhs[i]; r++) {
+            const CGScalars &c = D.cg[i][r];
+            if (c.pending || (c.active && c.rr < D.delta2 * c.maxrr)) need = 1;
+        }
+    *D.gate = need;
+    if (need) *D.count += 1;
+}
+
+hipError_t launch_decide(const DecideArgs &D, hipStream_t st)
+{
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, st, D);
+    return hipGetLastError();
 }
 
 hipError_t launch_finish(const FinishBatch &F, hipStream_t st)

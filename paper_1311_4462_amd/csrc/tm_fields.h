@@ -43,11 +43,13 @@ struct BlasBatch {
     int nprob;
     int total_blocks;
     int nf;
+    const int *gate;     // nullable: skip the launch when *gate == 0
     BlasProblem p[kMaxProblems];
 };
 
 hipError_t launch_blas(int op, int pa, int pb, const BlasBatch &B, hipStream_t st);
 hipError_t launch_finish(const FinishBatch &F, hipStream_t st);
+hipError_t launch_decide(const DecideArgs &D, hipStream_t st);
 
 // force
 hipError_t force_launch(int prec, int nf, int force_prec, void *F, void *G, const void *gauge0,

@@ -290,6 +290,7 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
 {
     using real = typename Prec<P>::real;
     __shared__ double red_sh[BS / 64];
+    if (B.gate && *B.gate == 0) return;   // gated launch not needed this iteration
 
     const int lb = B.xcd_remap ? xcd_logical_block(blockIdx.x, B.total_blocks) : (int)blockIdx.x;
     int pi = 0;

@@ -479,8 +479,9 @@ struct CGScalars {
     double alpha;
     double beta;
     double stop2;    // stop when rr <= stop2
+    double maxrr;    // largest rr since the last residual replacement
     int active;      // 0 once converged (updates become no-ops)
-    int pad;
+    int pending;     // converged in the iterated residual, not yet verified
 };
 
 enum FinOp { FIN_NONE = 0, FIN_STORE = 1, FIN_ALPHA = 2, FIN_BETA = 3, FIN_STORE_RR = 4, FIN_RELIABLE = 5 };
@@ -501,7 +502,20 @@ struct Reduce {
 
 struct FinishBatch {
     int nprob;
+    const int *gate;       // nullable: skip the launch when *gate == 0
     Reduce r[kMaxProblems];
+};
+
+// Device-side decision whether the next reliable update runs (mixed CG with
+// captured iterations): any active rhs whose rr fell below delta^2 maxrr, or
+// any rhs whose iterated residual converged and awaits verification.
+struct DecideArgs {
+    int nprob;
+    int nrhs[kMaxProblems];
+    CGScalars *cg[kMaxProblems];
+    double delta2;
+    int *gate;
+    int *count;            // number of updates decided (for reporting)
 };
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -550,7 +564,11 @@ __device__ void finish_reduce(const Reduce &rd, int nvec, int nblk, double *sh)
                     c.beta = (c.rr > 0.0) ? s / c.rr : 0.0;
                     c.rr_old = c.rr;
                     c.rr = s;
-                    if (s <= c.stop2) c.active = 0;
+                    c.maxrr = fmax(c.maxrr, s);
+                    if (s <= c.stop2) {
+                        c.active = 0;
+                        c.pending = 1;
+                    }
                 } else {
                     c.beta = 0.0;
                 }
@@ -560,14 +578,18 @@ __device__ void finish_reduce(const Reduce &rd, int nvec, int nblk, double *sh)
                 CGScalars &c = rd.cg[v];
                 c.beta = (c.rr_old > 0.0) ? s / c.rr_old : 0.0;
                 c.rr = s;
+                c.maxrr = s;
                 c.active = (s > c.stop2) ? 1 : 0;
+                c.pending = 0;
             } else if (rd.op == FIN_STORE_RR) {
                 // a fresh residual: restart the recurrence for this rhs
                 CGScalars &c = rd.cg[v];
                 c.rr = s;
                 c.rr_old = s;
+                c.maxrr = s;
                 c.beta = 0.0;
                 c.active = (s > c.stop2) ? 1 : 0;
+                c.pending = 0;
             }
         }
     }
@@ -594,6 +616,7 @@ struct HopProblem {
 struct HopBatch {
     int nprob;
     int total_blocks;
+    const int *gate;     // nullable: skip the launch when *gate == 0
     int epi;             // tm_epilogue
     int xcd_remap;       // 1: give every XCD a contiguous range of blocks
     HopProblem p[kMaxProblems];

@@ -303,6 +303,34 @@ def test_cg_multi_rhs_and_graph(api, ctx):
     assert np.array_equal(from_native(api, ctx, xg2, p, 0, 0, 4), from_native(api, ctx, xg, p, 0, 0, 4))
 
 
+@pytest.mark.parametrize("inner", [1, 2])
+def test_cg_mixed_graph_device_updates(api, ctx, inner):
+    """Mixed CG with captured iterations: reliable updates decided and gated on
+    the device every iteration; same tolerance as the host-driven solver."""
+    dims = (8, 8, 8, 8)
+    p = api.make_params(dims, 0.1615, 0.15, 0.19, api.NDEG)
+    U = inputs.gauge_field(dims, "near_unit", 1007)
+    g = api.Gauge(ctx, U, p, precs=(0, inner))
+    op = oparams(p)
+    b = O.project(inputs.gaussian_spinor(dims, 2, 2007, nrhs=2), dims, 0)
+    tb = to_native(api, ctx, b, p, 0, 0, 2)
+    xg = api.new_field(p, 0, 2)
+    rg = api.tm_cg(ctx, xg, tb, g, tol=1e-10, inner=inner, nrhs=2, graph_iters=6)
+    xh = api.new_field(p, 0, 2)
+    rh = api.tm_cg(ctx, xh, tb, g, tol=1e-10, inner=inner, nrhs=2)
+    x = from_native(api, ctx, xg, p, 0, 0, 2)
+    for r in range(2):
+        assert rg[r]["status"] == 0 and rg[r]["true_rel_res_normal"] <= 1e-10
+        assert rg[r]["reliable_updates"] >= 1
+        assert _oracle_normal_residual(op, U, x[r], b[r], "asym") <= 1.5e-10
+    # the device-decided schedule does not cost more than one graph of extra iterations
+    assert rg[0]["iters"] <= rh[0]["iters"] + 6
+    # two replays in a row give the same bits
+    xg2 = api.new_field(p, 0, 2)
+    api.tm_cg(ctx, xg2, tb, g, tol=1e-10, inner=inner, nrhs=2, graph_iters=6)
+    assert np.array_equal(from_native(api, ctx, xg2, p, 0, 0, 2), x)
+
+
 def test_cg_batched_uneven_lattices(api, ctx):
     """Several lattices of different size in one batched solve (each stage one
     launch over all problems) equal separate solves."""
