@@ -1,0 +1,102 @@
+"""Degenerate cases of the method and error paths of the C ABI, on the GPU.
+
+Degenerate cases against the oracle: kappa = 0 (M = R_ee, resp. 1), mu = 0
+(plain Wilson), eps = 0 doublet, periodic time boundary, the smallest lattice
+2^4, one site per block and a ragged last block.  Error paths are detected by
+argument validation before any kernel is launched."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1311_4462_amd import inputs
+from tests.gpu_util import TOL, from_native, oparams, rel, to_native
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_4462_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context()
+    yield c
+    c.close()
+
+
+CASES = [
+    # dims, kappa, mu, eps, flavor, antiperiodic
+    ((2, 2, 2, 2), 0.16, 0.1, 0.0, 1, True),
+    ((4, 2, 2, 2), 0.0, 0.5, 0.0, 1, True),          # kappa = 0
+    ((4, 4, 2, 6), 0.16, 0.0, 0.0, 1, True),         # Wilson
+    ((4, 4, 2, 6), 0.16, 0.2, 0.0, 2, True),         # doublet with eps = 0
+    ((6, 4, 4, 6), 0.16, 0.2, 0.3, 2, False),        # periodic time
+    ((2, 2, 2, 130), 0.15, 0.1, 0.0, -1, True),      # Lt >> block, thin lattice
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_degenerate_cases(api, ctx, case, prec):
+    dims, kappa, mu, eps, flavor, ap = case
+    p = api.make_params(dims, kappa, mu, eps, flavor, t_antiperiodic=ap)
+    op = oparams(p)
+    U = inputs.gauge_field(dims, "haar", 9)
+    g = api.Gauge(ctx, U, p, precs=(0, 1))
+    x = O.project(inputs.gaussian_spinor(dims, op.nf, 10), dims, 0)
+    t = to_native(api, ctx, x, p, prec, 0)
+    out = api.new_field(p, prec)
+    for pc in (0, 1):
+        for dag in (0, 1):
+            api.tm_mat_pc(ctx, out, t, g, prec, pc, dag)
+            ref = O.mat_pc(op, U, x, "asym" if pc == 0 else "sym", bool(dag))
+            assert rel(from_native(api, ctx, out, p, prec, 0)[0], ref) < TOL[prec]
+    if kappa == 0.0:
+        api.tm_mat_pc(ctx, out, t, g, prec, 0, 0)
+        assert rel(from_native(api, ctx, out, p, prec, 0)[0], O.twist(op, x, parity=0)) < TOL[prec]
+    g.close()
+
+
+def test_error_paths(api, ctx):
+    from paper_1311_4462_amd._lib import TMError
+    dims = (4, 4, 4, 4)
+    p = api.make_params(dims, 0.16, 0.1)
+    U = inputs.gauge_field(dims, "haar", 9)
+    g = api.Gauge(ctx, U, p, precs=(0,))
+    a = api.new_field(p, 0)
+    b = api.new_field(p, 0)
+    codes = []
+    for call in (
+        lambda: api.tm_dslash(ctx, a, b, g, 0, 2),                         # parity
+        lambda: api.tm_dslash(ctx, a, b, g, 0, 0, epi=api.EPI_RX_PLUS_KD),  # x missing
+        lambda: api.tm_dslash(ctx, a, a, g, 0, 0),                         # aliasing
+        lambda: api.tm_mat_pc(ctx, a, b, g, 1),                            # FP32 not built
+        lambda: api.tm_mat_pc(ctx, a, b, g, 0, pc=7),                      # bad pc
+        lambda: api.tm_cg(ctx, a, b, g, inner=2),                          # FP16 not built
+        lambda: api.tm_cg(ctx, a, b, g, tol=-1.0),                         # tol
+        lambda: api.tm_cg(ctx, a, a, g),                                   # aliasing
+        lambda: api.tm_force(ctx, a, 2, b, g, 0),                          # force precision
+    ):
+        with pytest.raises(TMError) as e:
+            call()
+        codes.append(e.value.code)
+    assert codes == [-3, -1, -1, -4, -1, -4, -1, -1, -4]
+    # a NaN source is reported, not iterated on
+    src = np.zeros((1,) + dims[::-1] + (1, 4, 3), complex)
+    src[0, 0, 0, 0, 0, 0, 0] = np.nan
+    tn = api.tm_spinor_pack(ctx, src, p, 0, 0)
+    with pytest.raises(TMError) as e:
+        api.tm_cg(ctx, a, tn, g)
+    assert e.value.code == -6
+    # maxiter reached: warning status, x and residuals still written
+    b2 = to_native(api, ctx, O.project(inputs.gaussian_spinor(dims, 1, 3), dims, 0), p, 0, 0)
+    with pytest.warns(UserWarning):
+        r = api.tm_cg(ctx, a, b2, g, maxiter=2)[0]
+    assert r["status"] == 1 and r["iters"] == 2 and 0 < r["true_rel_res_normal"] < 1
+    g.close()

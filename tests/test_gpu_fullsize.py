@@ -30,6 +30,7 @@ def api():
 @pytest.fixture(scope="module")
 def ctx(api):
     c = api.Context()
+    c.set_tuning(True)      # the launch configuration the benchmark times
     yield c
     c.close()
 
