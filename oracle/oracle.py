@@ -279,6 +279,82 @@ def solve(p: Params, U, b, pc="asym", tol=1e-12, maxiter=10000):
     return x_e + reconstruct(p, U, x_e, b), info
 
 
+# --- full-system solves (Sec. 2.2: solution types) ---------------------------
+
+def cg_full_normal(p: Params, U, b, tol=1e-12, maxiter=100000):
+    """CG on M^+ M x = b over the whole lattice with no preconditioning: the
+    plain definition of the MATDAG_MAT solution of Sec. 2.2.  Stops on the true
+    residual |b - M^+ M x| <= tol |b|."""
+    def A(v):
+        return full_M(p, U, full_M(p, U, v), dagger=True)
+
+    x = np.zeros_like(b)
+    r = b.copy()
+    bb = _nrm2(b)
+    pdir = r.copy()
+    rr = _nrm2(r)
+    it = 0
+    while it < maxiter:
+        if rr <= tol * tol * bb:
+            rtrue = b - A(x)
+            if _nrm2(rtrue) <= tol * tol * bb:
+                break
+            r = rtrue
+            rr = _nrm2(r)
+            pdir = r.copy()
+        ap = A(pdir)
+        alpha = rr / _dot(pdir, ap).real
+        x = x + alpha * pdir
+        r = r - alpha * ap
+        rr_new = _nrm2(r)
+        pdir = r + (rr_new / rr) * pdir
+        rr = rr_new
+        it += 1
+    return x, dict(iters=it, true_rel_res=np.sqrt(_nrm2(b - A(x)) / bb))
+
+
+def solve_full(p: Params, U, b, solution="mat", pc="asym", tol=1e-12):
+    """Solution of the full system: M psi = b ("mat", by the Schur route of
+    Eqs. 2.2-2.4) or M^+ M psi = b ("matdag_mat", plain CG on the full lattice)."""
+    if solution == "mat":
+        return solve(p, U, b, pc, tol)
+    if solution == "matdag_mat":
+        return cg_full_normal(p, U, b, tol)
+    raise ValueError(solution)
+
+
+# --- chiral basis (Sec. 2: conversion into the internal basis) ---------------
+#
+# The internal basis is the non-relativistic one of Sec. 2 (g4 diagonal).  The
+# chiral basis has g5 diagonal; the two are related by the real orthogonal
+# S = H (x) 1_2 on the spin index, H = [[1, 1], [1, -1]] / sqrt 2 acting on the
+# upper / lower pairs of spin components:
+#     psi_chiral = S psi_internal,   g_chiral = S g_internal S^T.
+# S is symmetric and its own inverse.
+
+CHIRAL_S = np.kron(np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0), np.eye(2)).astype(np.complex128)
+
+
+def _spin_apply(m, psi):
+    return np.einsum("ij,...jc->...ic", m, psi)
+
+
+def to_chiral(psi):
+    """Internal-basis spinor (canonical, spin axis -2) -> chiral basis."""
+    return _spin_apply(CHIRAL_S, psi)
+
+
+def from_chiral(psi):
+    """Chiral-basis spinor -> internal basis."""
+    return _spin_apply(CHIRAL_S.conj().T, psi)
+
+
+def chiral_gammas():
+    """g_mu (x, y, z, t) in the chiral basis, S g S^T of the internal ones."""
+    g = gammas()
+    return np.einsum("ij,mjk,lk->mil", CHIRAL_S, g, CHIRAL_S.conj())
+
+
 # --- gauge force -------------------------------------------------------------
 #
 # S = phi^+ (M^+ M)^-1 phi with M the preconditioned operator on even sites.

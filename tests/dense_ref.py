@@ -30,13 +30,23 @@ def site_index(c, dims):
     return x + lx * (y + ly * (z + lz * t))
 
 
-def dense_hop(dims, U, nf, tsign=-1.0, dagger=False):
-    """Dense Wilson hopping matrix D (or D^+) with antiperiodic-t factor tsign."""
+def chiral_gammas():
+    """A chiral basis (g5 = g1 g2 g3 g4 diagonal), written out:
+    g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0, 1], [1, 0]], g5 = diag(1, 1, -1, -1)."""
+    z = np.zeros((2, 2), complex)
+    g = [np.block([[z, -1j * s], [1j * s, z]]) for s in pauli()]
+    g.append(np.block([[z, np.eye(2)], [np.eye(2), z]]).astype(complex))
+    return g
+
+
+def dense_hop(dims, U, nf, tsign=-1.0, dagger=False, gam=None):
+    """Dense Wilson hopping matrix D (or D^+) with antiperiodic-t factor tsign
+    (gamma matrices of the basis of Sec. 2 unless `gam` gives another set)."""
     lx, ly, lz, lt = dims
     V = lx * ly * lz * lt
     n = nf * 12
     D = np.zeros((V * n, V * n), complex)
-    g = gammas()
+    g = gammas() if gam is None else gam
     one = np.eye(4)
     If = np.eye(nf)
     for t in range(lt):
@@ -60,9 +70,9 @@ def dense_hop(dims, U, nf, tsign=-1.0, dagger=False):
     return D
 
 
-def twist_block(nf, a, b, sign=1):
+def twist_block(nf, a, b, sign=1, gam=None):
     """R on (flavour, spin): 1 + i a g5 t3 + b t1, or 1 + i*sign*a*g5 for one flavour."""
-    g = gammas()
+    g = gammas() if gam is None else gam
     g5 = g[0] @ g[1] @ g[2] @ g[3]
     if nf == 1:
         return np.eye(4) + 1j * sign * a * g5
@@ -70,12 +80,12 @@ def twist_block(nf, a, b, sign=1):
     return np.eye(8) + 1j * a * np.kron(t3, g5) + b * np.kron(t1, np.eye(4))
 
 
-def dense_M(dims, U, kappa, mu, eps=0.0, nf=1, sign=1, tsign=-1.0):
+def dense_M(dims, U, kappa, mu, eps=0.0, nf=1, sign=1, tsign=-1.0, gam=None):
     """Dense M = R - kappa D (Eq. 2.1 times 2 kappa) on the canonical index."""
     V = int(np.prod(dims))
     a, b = 2 * kappa * mu, 2 * kappa * eps
-    R = np.kron(np.eye(V), np.kron(twist_block(nf, a, b, sign), np.eye(3)))
-    return R - kappa * dense_hop(dims, U, nf, tsign)
+    R = np.kron(np.eye(V), np.kron(twist_block(nf, a, b, sign, gam), np.eye(3)))
+    return R - kappa * dense_hop(dims, U, nf, tsign, gam=gam)
 
 
 def parity_index(dims, parity, nf):
