@@ -87,12 +87,15 @@ def cpu_baseline(U, b_e, dims, vh, budget_s=15.0):
                       f"{'x'.join(map(str, dims))} (median {t:.2f} s each)"}
 
 
-def mat_pc_rates(torch, api, ctx, g, p, precs, reps, flops_site):
+BYTES_PER_REAL = {0: 8, 1: 4, 2: 2, 3: 2}     # FP64, FP32, FP16, BF16
+
+
+def mat_pc_rates(torch, api, ctx, g, p, precs, reps, flops_site, recon=12):
     """Per-precision asymmetric M apply on a resident field: us, Gflop/s, algorithmic GB/s."""
     import numpy as np
     nf = 2 if p.flavor == api.NDEG else 1
     vh = int(np.prod(tuple(p.dims))) // 2
-    L = {api.FP64: 96, api.FP32: 48, api.FP16: 24, api.BF16: 24}
+    L = {q: recon * BYTES_PER_REAL[q] for q in (api.FP64, api.FP32, api.FP16, api.BF16)}
     S = {api.FP64: 192 * nf, api.FP32: 96 * nf, api.FP16: 52 * nf, api.BF16: 52 * nf}
     src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
     out = {}
@@ -104,6 +107,30 @@ def mat_pc_rates(torch, api, ctx, g, p, precs, reps, flops_site):
                                      "gbs": round((16 * L[prec] + 5 * S[prec]) * vh / t / 1e9, 1)}
         del x, y
     del src
+    return out
+
+
+def operator_variants(torch, api, ctx, U, p, reps):
+    """us per apply of the preconditioned operator, asym / sym, with and without
+    dagger, FP64 and FP32, for 18-, 12- and 8-real links."""
+    Ut = torch.from_numpy(U).cuda()
+    src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
+    out = {}
+    for recon in (18, 12, 8):
+        g = api.Gauge(ctx, Ut, p, recon=recon, precs=(api.FP64, api.FP32))
+        for prec in (api.FP64, api.FP32):
+            x = api.tm_spinor_pack(ctx, src, p, prec, 0)
+            y = api.new_field(p, prec)
+            row = {}
+            for pc, pcn in ((api.ASYM, "asym"), (api.SYM, "sym")):
+                for dag in (0, 1):
+                    t = time_launches(torch, lambda: api.tm_mat_pc(ctx, y, x, g, prec, pc, dag), reps)
+                    row[pcn + ("_dag" if dag else "")] = round(t * 1e6, 2)
+            out[f"{api.PREC_NAMES[prec]}_r{recon}"] = row
+            del x, y
+        g.close()
+    del Ut, src
+    log(f"operator variants (us): {out}")
     return out
 
 
@@ -126,6 +153,15 @@ def cg_comparison(torch, api, inputs, reps=3):
     gd = api.Gauge(ctx, Ut, pd, recon=12, precs=(api.FP32,))
     rates["deg"] = mat_pc_rates(torch, api, ctx, gd, pd, (api.FP32,), 20, FLOPS_PER_SITE["deg_asym"])
     gd.close()
+    # 8-real links: the same applies with a third fewer link bytes
+    g8 = api.Gauge(ctx, Ut, p, recon=8, precs=(api.FP32, api.FP16))
+    rates["nd_recon8"] = mat_pc_rates(torch, api, ctx, g8, p, (api.FP32, api.FP16), 20,
+                                      FLOPS_PER_SITE["nd"], recon=8)
+    g8.close()
+    gd8 = api.Gauge(ctx, Ut, pd, recon=8, precs=(api.FP32,))
+    rates["deg_recon8"] = mat_pc_rates(torch, api, ctx, gd8, pd, (api.FP32,), 20,
+                                       FLOPS_PER_SITE["deg_asym"], recon=8)
+    gd8.close()
     log(f"32^3x64 mat_pc rates: {rates}")
     del Ut
     b = inputs.gaussian_spinor(dims, 2, 2003)
@@ -339,6 +375,10 @@ def main():
     extra["mat_pc_fp64"] = {"us": round(t64 * 1e6, 2), "gflops": round(flops / t64 / 1e9, 1),
                             "gbs": round((16 * 96 + 5 * 192) * vh / t64 / 1e9, 1)}
     del x64, y64
+    extra["variants_24x24x24x48_us"] = operator_variants(torch, api, ctx, U, p, a.kernel_reps)
+    v8 = extra["variants_24x24x24x48_us"]["f32_r8"]["asym"]
+    extra["mat_pc_fp32_recon8"] = {"us": v8, "gflops": round(flops / (v8 * 1e-6) / 1e9, 1),
+                                   "gbs": round((16 * 32 + 5 * 96) * vh / (v8 * 1e-6) / 1e9, 1)}
     g.close()
     ctx.close()
     del U

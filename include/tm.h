@@ -37,7 +37,8 @@
  *   half of the site's bytes, so a time hop reads only half of a neighbour.
  *   Packed links (library owned): per parity [mu][cb] rows of 16 bytes, then
  *   narrower rows for what does not fill 16 bytes; 12-real storage keeps rows
- *   0 and 1 of each link.
+ *   0 and 1 of each link, 8-real storage four complex slots (FP32: two rows,
+ *   FP16/BF16: one row).
  *   Canonical (host-side exchange) layout, complex128, full lattice:
  *       spinor [nrhs][lex][nf][4][3], links [mu][lex][3][3] (row-major).
  *
@@ -77,6 +78,19 @@ typedef enum { TM_PC_ASYM = 0, TM_PC_SYM = 1 } tm_pc;
  * TM_SOLUTION_MAT: x solves M x = b (CG on M^+ M x = M^+ b);
  * TM_SOLUTION_MATDAG_MAT: x solves M^+ M x = b.                              */
 typedef enum { TM_SOLUTION_MAT = 0, TM_SOLUTION_MATDAG_MAT = 1 } tm_solution;
+/* Solve type of tm_solve (Sec. 2.2, solver_type): which residual of the
+ * preconditioned system the tolerance bounds.
+ * TM_SOLVE_NORMOP_PC: the normal residual |M^+b - M^+M x| / |M^+b| (as tm_cg);
+ * TM_SOLVE_DIRECT_PC: the system's own residual |b - M x| / |b| (CG restarted
+ * from its current x with a tighter normal tolerance until this holds).      */
+typedef enum { TM_SOLVE_NORMOP_PC = 0, TM_SOLVE_DIRECT_PC = 1 } tm_solve_type;
+/* Spin basis of canonical spinors (Sec. 2: the library computes in the
+ * non-relativistic basis and converts from a chiral one on the way in/out).
+ * TM_BASIS_CHIRAL: g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0, 1], [1, 0]],
+ * g5 = diag(1, 1, -1, -1); psi_chiral = S psi_internal with the real
+ * orthogonal, self-inverse S = H (x) 1_2, H = [[1, 1], [1, -1]] / sqrt 2 on
+ * the (upper, lower) spin pairs: components 0 and 2, 1 and 3 mix.          */
+typedef enum { TM_BASIS_INTERNAL = 0, TM_BASIS_CHIRAL = 1 } tm_basis;
 
 /* Epilogue of tm_dslash, with A = D in (or D^+ in), x the optional field of the
  * output parity and R, R^-1 daggered when dagger = 1:                          */
@@ -118,7 +132,18 @@ typedef struct {
     double true_rel_res_normal;   /* |M^+b - M^+M x| / |M^+b|, FP64, recomputed  */
     double true_rel_res_pc;       /* |b - M x| / |b| (MATDAG_MAT: |b - M^+M x|/|b|) */
     double seconds;               /* wall time of the solve (host clock)         */
+    double true_rel_res_full;     /* tm_solve: |b - M x| / |b| (MATDAG_MAT:
+                                     |b - M^+M x| / |b|) over both parities;
+                                     tm_cg: -1                                    */
 } tm_cg_result;
+
+typedef struct {
+    tm_cg_params cg;      /* pc, tol, maxiter, inner, delta, nrhs, graph_iters,
+                             check_every of every CG run (its use_x0 and
+                             solution are set by tm_solve)                    */
+    int solve_type;       /* tm_solve_type                                      */
+    int solution;         /* tm_solution of the full system                     */
+} tm_solve_params;
 
 typedef struct tm_ctx tm_ctx;
 typedef struct tm_gauge tm_gauge;
@@ -133,10 +158,15 @@ const char *tm_last_error(tm_ctx *ctx);
 
 /* Gauge field + operator parameters (the Dirac operator object, Sec. 2.1).
  * links_dev: complex128 canonical links [4][V][3][3] on the device (read only
- * during the call).  recon: 18 (full links) or 12 (rows 0 and 1 stored, row 2
- * rebuilt as conj(row0 x row1), Sec. 3).  prec_mask: bit (1 << tm_prec) for
- * every precision to build.  Validates dims (TM_ERR_DIMS) and the twist
- * (TM_ERR_SINGULAR).  Synchronises the stream.                                */
+ * during the call).  recon (Sec. 3, link reconstruction): 18 (full links),
+ * 12 (rows 0 and 1 stored, row 2 rebuilt as conj(row0 x row1)) or 8 (U01,
+ * U02, U10 and the phases of U00 and U20 stored; the other entries rebuilt
+ * from unit rows/columns, row orthogonality and det U = 1; the phases are
+ * 16-bit fixed point in FP16/BF16).  8 needs |U01|^2 + |U02|^2 >= 1e-10 on
+ * every link (else TM_ERR_ARG: e.g. the unit gauge field) and is not read by
+ * tm_force.  prec_mask: bit (1 << tm_prec) for every precision to build.
+ * Validates dims (TM_ERR_DIMS) and the twist (TM_ERR_SINGULAR).  Synchronises
+ * the stream.                                                                 */
 int tm_gauge_create(tm_ctx *ctx, tm_gauge **g, const void *links_dev, const tm_params *p,
                     int recon, unsigned prec_mask);
 int tm_gauge_destroy(tm_gauge *g);
@@ -147,11 +177,13 @@ size_t tm_gauge_bytes(const tm_gauge *g, tm_prec prec);
 size_t tm_spinor_bytes(const tm_params *p, tm_prec prec, int nrhs);
 
 /* Canonical complex128 full-lattice field [nrhs][V][nf][4][3] (device) <->
- * native field of one parity.  Unpack writes only the sites of that parity.  */
+ * native field of one parity.  Unpack writes only the sites of that parity.
+ * basis (tm_basis) is the spin basis of the canonical field; the conversion
+ * is applied in FP64 on the way (Sec. 2, converting routines).               */
 int tm_spinor_pack(tm_ctx *ctx, void *dst_native, const void *src_canonical,
-                   const tm_params *p, tm_prec prec, int parity, int nrhs);
+                   const tm_params *p, tm_prec prec, int parity, int nrhs, int basis);
 int tm_spinor_unpack(tm_ctx *ctx, void *dst_canonical, const void *src_native,
-                     const tm_params *p, tm_prec prec, int parity, int nrhs);
+                     const tm_params *p, tm_prec prec, int parity, int nrhs, int basis);
 
 /* Fused hop (Sec. 2.1, "fused kernels"): out (parity out_parity) = epilogue of
  * D in or D^+ in (in has the other parity).  twist_on_load = 1 applies R^-1
@@ -202,6 +234,24 @@ int tm_cg(tm_ctx *ctx, void *x_e, const void *b_e, const tm_gauge *g, const tm_c
 int tm_cg_batched(tm_ctx *ctx, int nproblems, const tm_gauge *const *g, void *const *x_e,
                   const void *const *b_e, const int *nrhs, const tm_cg_params *par,
                   tm_cg_result *res);
+
+/* Full-system solve (Sec. 2.2, solution_type x solver_type; Eqs. 2.2-2.4).
+ * b_e, b_o: FP64 native source halves; x_e, x_o: FP64 native solution halves
+ * (written; must not alias the sources).  nrhs = par->cg.nrhs.
+ *   TM_SOLUTION_MAT: M x = b.  b^ = b_e + kappa D_eo R_oo^-1 b_o (sym: R_ee^-1
+ *     times that), CG on the preconditioned system, then
+ *     x_o = R_oo^-1 (b_o + kappa D_oe x_e).
+ *   TM_SOLUTION_MATDAG_MAT: M^+ M x = b, as two solves M^+ y = b, M x = y.  The
+ *     first takes the Schur route of M^+ (R^+, D^+ in place of R, D): with A
+ *     the preconditioned operator, z solves A^+ A z = c for
+ *     c = b_e + kappa D^+_eo R_oo^-+ b_o, y_e = A z (sym: R_ee^-+ A z) and
+ *     y_o = R_oo^-+ (b_o + kappa D^+_oe y_e).
+ * res[nrhs]: iterations and reliable updates summed over every CG run,
+ * residuals of the last one, and true_rel_res_full.  Returns TM_NOT_CONVERGED
+ * if a CG run missed its tolerance (x still written).  Workspace: up to five
+ * FP64 fields of one parity besides tm_cg's.                                  */
+int tm_solve(tm_ctx *ctx, void *x_e, void *x_o, const void *b_e, const void *b_o,
+             const tm_gauge *g, const tm_solve_params *par, tm_cg_result *res);
 
 /* Native-field BLAS used by the solvers, exposed for tests and clients.
  * Results are written to host memory (synchronous).                           */

@@ -31,7 +31,11 @@ class tm_cg_params(ctypes.Structure):
 class tm_cg_result(ctypes.Structure):
     _fields_ = [("iters", c_int), ("reliable_updates", c_int),
                 ("true_rel_res_normal", c_double), ("true_rel_res_pc", c_double),
-                ("seconds", c_double)]
+                ("seconds", c_double), ("true_rel_res_full", c_double)]
+
+
+class tm_solve_params(ctypes.Structure):
+    _fields_ = [("cg", tm_cg_params), ("solve_type", c_int), ("solution", c_int)]
 
 
 P = ctypes.POINTER
@@ -46,8 +50,10 @@ _SIGS = {
     "tm_gauge_destroy": (c_int, [c_void_p]),
     "tm_gauge_bytes": (c_size_t, [c_void_p, c_int]),
     "tm_spinor_bytes": (c_size_t, [P(tm_params), c_int, c_int]),
-    "tm_spinor_pack": (c_int, [c_void_p, c_void_p, c_void_p, P(tm_params), c_int, c_int, c_int]),
-    "tm_spinor_unpack": (c_int, [c_void_p, c_void_p, c_void_p, P(tm_params), c_int, c_int, c_int]),
+    "tm_spinor_pack": (c_int, [c_void_p, c_void_p, c_void_p, P(tm_params), c_int, c_int, c_int,
+                               c_int]),
+    "tm_spinor_unpack": (c_int, [c_void_p, c_void_p, c_void_p, P(tm_params), c_int, c_int, c_int,
+                                 c_int]),
     "tm_dslash": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
                           c_int, c_void_p, c_double, c_int]),
     "tm_mat_pc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
@@ -58,6 +64,8 @@ _SIGS = {
     "tm_cg": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, P(tm_cg_params), P(tm_cg_result)]),
     "tm_cg_batched": (c_int, [c_void_p, c_int, P(c_void_p), P(c_void_p), P(c_void_p), P(c_int),
                               P(tm_cg_params), P(tm_cg_result)]),
+    "tm_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                         P(tm_solve_params), P(tm_cg_result)]),
     "tm_norm2": (c_int, [c_void_p, P(c_double), c_void_p, P(tm_params), c_int, c_int]),
     "tm_dot": (c_int, [c_void_p, P(c_double), c_void_p, c_void_p, P(tm_params), c_int, c_int]),
     "tm_convert": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, P(tm_params), c_int]),

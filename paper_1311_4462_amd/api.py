@@ -12,12 +12,14 @@ import warnings
 import numpy as np
 import torch
 
-from ._lib import TMError, lib, tm_cg_params, tm_cg_result, tm_params
+from ._lib import TMError, lib, tm_cg_params, tm_cg_result, tm_params, tm_solve_params
 
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 PLUS, MINUS, NDEG = 1, -1, 2
 ASYM, SYM = 0, 1
 SOLUTION_MAT, SOLUTION_MATDAG_MAT = 0, 1
+SOLVE_NORMOP_PC, SOLVE_DIRECT_PC = 0, 1
+BASIS_INTERNAL, BASIS_CHIRAL = 0, 1
 EPI_NONE, EPI_TWINV, EPI_RX_PLUS_KD, EPI_X_PLUS_K_TWINV_D, EPI_TWINV_X_PLUS_KD, EPI_X_PLUS_KD = range(6)
 TM_OK, TM_NOT_CONVERGED = 0, 1
 PREC_NAMES = {FP64: "f64", FP32: "f32", FP16: "f16", BF16: "bf16"}
@@ -140,7 +142,7 @@ def canonical_shape(params: tm_params, nrhs: int = 1):
 
 
 def tm_spinor_pack(ctx: Context, canonical, params: tm_params, prec: int, parity: int,
-                   nrhs: int = 1, out=None) -> torch.Tensor:
+                   nrhs: int = 1, out=None, basis: int = BASIS_INTERNAL) -> torch.Tensor:
     if isinstance(canonical, np.ndarray):
         canonical = torch.from_numpy(np.ascontiguousarray(canonical))
     canonical = canonical.to("cuda").contiguous()
@@ -148,16 +150,16 @@ def tm_spinor_pack(ctx: Context, canonical, params: tm_params, prec: int, parity
     assert canonical.numel() == int(np.prod(canonical_shape(params, nrhs)))
     out = new_field(params, prec, nrhs) if out is None else out
     ctx.check(lib().tm_spinor_pack(ctx.h, _ptr(out), _ptr(canonical), ctypes.byref(params), prec,
-                                   parity, nrhs), "tm_spinor_pack")
+                                   parity, nrhs, basis), "tm_spinor_pack")
     return out
 
 
 def tm_spinor_unpack(ctx: Context, native, params: tm_params, prec: int, parity: int,
-                     nrhs: int = 1, out=None) -> torch.Tensor:
+                     nrhs: int = 1, out=None, basis: int = BASIS_INTERNAL) -> torch.Tensor:
     if out is None:
         out = torch.zeros(canonical_shape(params, nrhs), dtype=torch.complex128, device="cuda")
     ctx.check(lib().tm_spinor_unpack(ctx.h, _ptr(out), _ptr(native), ctypes.byref(params), prec,
-                                     parity, nrhs), "tm_spinor_unpack")
+                                     parity, nrhs, basis), "tm_spinor_unpack")
     return out
 
 
@@ -206,7 +208,8 @@ def _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_
 def _results(res, n):
     return [dict(iters=res[i].iters, reliable_updates=res[i].reliable_updates,
                  true_rel_res_normal=res[i].true_rel_res_normal,
-                 true_rel_res_pc=res[i].true_rel_res_pc, seconds=res[i].seconds) for i in range(n)]
+                 true_rel_res_pc=res[i].true_rel_res_pc, seconds=res[i].seconds,
+                 true_rel_res_full=res[i].true_rel_res_full) for i in range(n)]
 
 
 def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64, delta=0.0,
@@ -234,6 +237,22 @@ def tm_cg_batched(ctx, gauges, xs, bs, nrhs, pc=ASYM, tol=1e-10, maxiter=5000, i
     rc = ctx.check(lib().tm_cg_batched(ctx.h, n, ga, xa, ba, na, ctypes.byref(p), res),
                    "tm_cg_batched")
     out = _results(res, total)
+    for o in out:
+        o["status"] = rc
+    return out
+
+
+def tm_solve(ctx, x_e, x_o, b_e, b_o, gauge: Gauge, solution=SOLUTION_MAT,
+             solve_type=SOLVE_NORMOP_PC, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64, delta=0.0,
+             nrhs=1, graph_iters=0, check_every=1):
+    """Full-system solve M x = b or M^+ M x = b; all four fields FP64 native."""
+    p = tm_solve_params()
+    p.cg = _cg_params(pc, tol, maxiter, inner, delta, False, nrhs, graph_iters, check_every)
+    p.solve_type, p.solution = solve_type, solution
+    res = (tm_cg_result * nrhs)()
+    rc = ctx.check(lib().tm_solve(ctx.h, _ptr(x_e), _ptr(x_o), _ptr(b_e), _ptr(b_o), gauge.h,
+                                  ctypes.byref(p), res), "tm_solve")
+    out = _results(res, nrhs)
     for o in out:
         o["status"] = rc
     return out

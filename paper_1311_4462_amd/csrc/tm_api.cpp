@@ -221,7 +221,7 @@ struct HopCfg {
 std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon)
 {
     if (twl) return {{256, true}};
-    std::vector<int> bss = (recon != 12) ? std::vector<int>{256}
+    std::vector<int> bss = (recon == 18) ? std::vector<int>{256}
                            : (nr == 1) ? std::vector<int>{64, 128, 256} : std::vector<int>{128, 256};
     std::vector<HopCfg> out;
     for (int b : bss) {
@@ -621,8 +621,12 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const t
     TM_TRY(check_params(ctx, p));
     if (p->t_antiperiodic != 0 && p->t_antiperiodic != 1)
         return fail(ctx, TM_ERR_ARG, "t_antiperiodic must be 0 or 1");
-    if (recon != 12 && recon != 18) return fail(ctx, TM_ERR_ARG, "recon must be 12 or 18");
+    if (recon != 12 && recon != 18 && recon != 8) return fail(ctx, TM_ERR_ARG, "recon must be 8, 12 or 18");
     if (prec_mask == 0 || (prec_mask & ~0xFu)) return fail(ctx, TM_ERR_PREC, "bad precision mask");
+    int rc = TM_OK;
+    int *bad = (int *)workspace(ctx, "gauge_bad", sizeof(int), &rc);
+    if (!bad) return rc;
+    TM_HIP(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
     tm_gauge *g = new tm_gauge();
     g->p = *p;
     g->recon = recon;
@@ -638,16 +642,23 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const t
             }
         }
         hipError_t e = gauge_pack(prec, recon, g->links[prec][0], g->links[prec][1], links_dev,
-                                  p->dims, g->vh, ctx->stream);
+                                  p->dims, g->vh, bad, ctx->stream);
         if (e != hipSuccess) {
             tm_gauge_destroy(g);
             return fail(ctx, TM_ERR_HIP, "gauge pack: %s", hipGetErrorString(e));
         }
     }
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    int hbad = 0;
+    hipError_t e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         tm_gauge_destroy(g);
         return fail(ctx, TM_ERR_HIP, "gauge pack: %s", hipGetErrorString(e));
+    }
+    if (hbad) {
+        tm_gauge_destroy(g);
+        return fail(ctx, TM_ERR_ARG, "8-real links: a link has |U01|^2 + |U02|^2 < 1e-10 "
+                                     "(not representable; use 12 or 18)");
     }
     *gout = g;
     return TM_OK;
@@ -679,7 +690,7 @@ size_t tm_spinor_bytes(const tm_params *p, tm_prec prec, int nrhs)
 }
 
 int tm_spinor_pack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, tm_prec prec,
-                   int parity, int nrhs)
+                   int parity, int nrhs, int basis)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_params(ctx, p));
@@ -687,15 +698,16 @@ int tm_spinor_pack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, 
     if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
     if (parity != 0 && parity != 1) return fail(ctx, TM_ERR_PARITY, "bad parity %d", parity);
     if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    if (basis != TM_BASIS_INTERNAL && basis != TM_BASIS_CHIRAL) return fail(ctx, TM_ERR_ARG, "bad basis %d", basis);
     const uint32_t vh = half_volume(*p);
     const int nf = nflav(*p);
     TM_HIP(ctx, spinor_pack(prec, sptr(dst, prec, vh, nf, nrhs), src, p->dims, vh, parity, nf, nrhs,
-                            ctx->stream));
+                            basis, ctx->stream));
     return TM_OK;
 }
 
 int tm_spinor_unpack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, tm_prec prec,
-                     int parity, int nrhs)
+                     int parity, int nrhs, int basis)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_params(ctx, p));
@@ -703,10 +715,11 @@ int tm_spinor_unpack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p
     if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
     if (parity != 0 && parity != 1) return fail(ctx, TM_ERR_PARITY, "bad parity %d", parity);
     if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    if (basis != TM_BASIS_INTERNAL && basis != TM_BASIS_CHIRAL) return fail(ctx, TM_ERR_ARG, "bad basis %d", basis);
     const uint32_t vh = half_volume(*p);
     const int nf = nflav(*p);
     TM_HIP(ctx, spinor_unpack(prec, dst, sptr(src, prec, vh, nf, nrhs), p->dims, vh, parity, nf,
-                              nrhs, ctx->stream));
+                              nrhs, basis, ctx->stream));
     return TM_OK;
 }
 
@@ -1323,6 +1336,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             o.true_rel_res_normal = pr[i].cc[r] > 0 ? std::sqrt(rn[i][r] / pr[i].cc[r]) : 0.0;
             o.true_rel_res_pc = bb[i][r] > 0 ? std::sqrt(rp[i][r] / bb[i][r]) : 0.0;
             o.seconds = secs;
+            o.true_rel_res_full = -1.0;
             if (!std::isfinite(o.true_rel_res_normal)) status = fail(ctx, TM_ERR_NAN, "non-finite residual");
             if (status == TM_OK && o.true_rel_res_normal > par->tol * 1.0000001) status = TM_NOT_CONVERGED;
         }
@@ -1415,6 +1429,191 @@ int tm_cg_batched(tm_ctx *ctx, int nproblems, const tm_gauge *const *g, void *co
     return cg_run(ctx, pr, par, res);
 }
 
+namespace {
+
+// FP64 field of one parity from the solver's own workspace
+void *solve_field(tm_ctx *ctx, const char *tag, const tm_gauge *g, int nrhs, int *rc)
+{
+    char name[64];
+    snprintf(name, sizeof(name), "solve_%s", tag);
+    return workspace(ctx, name, spinor_field_bytes(TM_FP64, g->vh, g->nf, nrhs), rc);
+}
+
+// |a - b|^2 per rhs (b may be null: |a|^2) of FP64 fields into host h[nrhs];
+// d receives a - b.
+int diff_norm2(tm_ctx *ctx, const tm_gauge *g, const void *a, const void *b, void *d, int nrhs,
+               std::vector<double> &h)
+{
+    int rc = TM_OK;
+    double *dres = (double *)workspace(ctx, "solve_norms", (size_t)nrhs * sizeof(double), &rc);
+    if (!dres) return rc;
+    double *hs = host_scratch(ctx, nrhs, &rc);
+    if (!hs) return rc;
+    BlasCall c{g->vh, nrhs, {a, b, d, nullptr}, FIN_STORE, nullptr, dres};
+    TM_TRY(blas1(ctx, OP_RESIDUAL, TM_FP64, TM_FP64, g->nf, c));
+    TM_HIP(ctx, hipMemcpyAsync(hs, dres, nrhs * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    h.assign(hs, hs + nrhs);
+    return TM_OK;
+}
+
+// out = M in (dagger: M^+ in) on both parities, FP64:
+//   out_e = R in_e - kappa D_eo in_o,  out_o = R in_o - kappa D_oe in_e
+int full_op64(tm_ctx *ctx, const tm_gauge *g, void *oe, void *oo, const void *ie, const void *io,
+              int dagger, int nrhs)
+{
+    const double k = -g->p.kappa;
+    TM_TRY(hop1(ctx, HopCall{g, TM_FP64, 0, dagger, 0, TM_EPI_RX_PLUS_KD, io, oe, ie, k, nrhs,
+                             FIN_NONE, nullptr, nullptr}));
+    return hop1(ctx, HopCall{g, TM_FP64, 1, dagger, 0, TM_EPI_RX_PLUS_KD, ie, oo, io, k, nrhs,
+                             FIN_NONE, nullptr, nullptr});
+}
+
+// Accumulates one CG run's report into the solve's report.
+void add_report(tm_cg_result *acc, const tm_cg_result *r, int nrhs)
+{
+    for (int i = 0; i < nrhs; i++) {
+        acc[i].iters += r[i].iters;
+        acc[i].reliable_updates += r[i].reliable_updates;
+        acc[i].true_rel_res_normal = r[i].true_rel_res_normal;
+        acc[i].true_rel_res_pc = r[i].true_rel_res_pc;
+    }
+}
+
+// CG on one preconditioned system: x solves A x = b (solution MAT) or
+// A^+ A x = b (MATDAG_MAT).  With the direct solve type a MAT solve is
+// restarted from its x, with the normal tolerance scaled down, until
+// |b - A x| <= tol |b| for every rhs (at most six runs, normal tolerance
+// >= 1e-15).
+int solve_pc(tm_ctx *ctx, const tm_gauge *g, void *x, const void *b, const tm_solve_params *par,
+             int solution, tm_cg_result *acc, int *status)
+{
+    const int nrhs = par->cg.nrhs;
+    tm_cg_params q = par->cg;
+    q.solution = solution;
+    q.use_x0 = 0;
+    std::vector<tm_cg_result> r(nrhs);
+    std::vector<CGProblem> pr(1);
+    for (int run = 0;; run++) {
+        pr[0] = CGProblem{};
+        pr[0].g = g;
+        pr[0].nrhs = nrhs;
+        pr[0].x = x;
+        pr[0].b = b;
+        const int rc = cg_run(ctx, pr, &q, r.data());
+        if (rc < 0) return rc;
+        add_report(acc, r.data(), nrhs);
+        if (rc == TM_NOT_CONVERGED) {
+            *status = TM_NOT_CONVERGED;
+            return TM_OK;
+        }
+        if (par->solve_type != TM_SOLVE_DIRECT_PC || solution != TM_SOLUTION_MAT) return TM_OK;
+        double worst = 0.0;
+        for (int i = 0; i < nrhs; i++) worst = std::max(worst, r[i].true_rel_res_pc / par->cg.tol);
+        if (worst <= 1.0) return TM_OK;
+        int used = 0;
+        for (int i = 0; i < nrhs; i++) used = std::max(used, acc[i].iters);
+        if (run == 5 || q.tol <= 1e-15 || used >= par->cg.maxiter) {
+            *status = TM_NOT_CONVERGED;
+            return TM_OK;
+        }
+        q.tol = std::max(1e-15, q.tol / worst * 0.5);
+        q.use_x0 = 1;
+        q.maxiter = par->cg.maxiter - used;
+    }
+}
+
+}  // namespace
+
+int tm_solve(tm_ctx *ctx, void *x_e, void *x_o, const void *b_e, const void *b_o, const tm_gauge *g,
+             const tm_solve_params *par, tm_cg_result *res)
+{
+    if (!ctx) return TM_ERR_ARG;
+    if (!par) return fail(ctx, TM_ERR_ARG, "null solve params");
+    TM_TRY(check_cg(ctx, g, &par->cg));
+    if (!x_e || !x_o || !b_e || !b_o || !res) return fail(ctx, TM_ERR_ARG, "null pointer");
+    if (x_e == x_o || x_e == b_e || x_e == b_o || x_o == b_e || x_o == b_o || b_e == b_o)
+        return fail(ctx, TM_ERR_ARG, "solution and source halves must be distinct buffers");
+    if (par->solve_type != TM_SOLVE_NORMOP_PC && par->solve_type != TM_SOLVE_DIRECT_PC)
+        return fail(ctx, TM_ERR_ARG, "bad solve type");
+    if (par->solution != TM_SOLUTION_MAT && par->solution != TM_SOLUTION_MATDAG_MAT)
+        return fail(ctx, TM_ERR_ARG, "bad solution type");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nrhs = par->cg.nrhs;
+    const int pc = par->cg.pc;
+    const double kappa = g->p.kappa;
+    StreamSwap sw(ctx, par->cg.graph_iters > 0);
+    for (int i = 0; i < nrhs; i++) res[i] = tm_cg_result{};
+    int status = TM_OK;
+    int rc = TM_OK;
+    void *e0 = solve_field(ctx, "e0", g, nrhs, &rc);
+    void *e1 = solve_field(ctx, "e1", g, nrhs, &rc);
+    void *o0 = solve_field(ctx, "o0", g, nrhs, &rc);
+    if (!e0 || !e1 || !o0) return rc;
+    // source of the M x = y stage: b itself, or y from the M^+ y = b stage
+    const void *src_e = b_e, *src_o = b_o;
+    void *y_e = nullptr, *y_o = nullptr;
+    if (par->solution == TM_SOLUTION_MATDAG_MAT) {
+        y_e = solve_field(ctx, "ye", g, nrhs, &rc);
+        y_o = solve_field(ctx, "yo", g, nrhs, &rc);
+        if (!y_e || !y_o) return rc;
+        // c = b_e + kappa D^+_eo R_oo^-+ b_o   (e0)
+        TM_TRY(hop1(ctx, HopCall{g, TM_FP64, 0, 1, 1, TM_EPI_X_PLUS_KD, b_o, e0, b_e, kappa, nrhs,
+                                 FIN_NONE, nullptr, nullptr}));
+        // z: A^+ A z = c   (x_e serves as z)
+        TM_TRY(solve_pc(ctx, g, x_e, e0, par, TM_SOLUTION_MATDAG_MAT, res, &status));
+        // y_e = A z, sym: R_ee^-+ A z
+        if (pc == TM_PC_ASYM) {
+            TM_TRY(mat_pc_batch(ctx, &g, &y_e, (const void *const *)&x_e, &nrhs, 1, TM_FP64, pc, 0,
+                                FIN_NONE, nullptr));
+        } else {
+            TM_TRY(mat_pc_batch(ctx, &g, &e1, (const void *const *)&x_e, &nrhs, 1, TM_FP64, pc, 0,
+                                FIN_NONE, nullptr));
+            TM_HIP(ctx, twist_apply(TM_FP64, g->nf, sptr(y_e, TM_FP64, g->vh, g->nf, nrhs),
+                                    sptr(e1, TM_FP64, g->vh, g->nf, nrhs), g->vh, nrhs,
+                                    make_twist(g->p, 1), 1, ctx->stream));
+        }
+        // y_o = R_oo^-+ (b_o + kappa D^+_oe y_e)
+        TM_TRY(hop1(ctx, HopCall{g, TM_FP64, 1, 1, 0, TM_EPI_TWINV_X_PLUS_KD, y_e, y_o, b_o, kappa,
+                                 nrhs, FIN_NONE, nullptr, nullptr}));
+        src_e = y_e;
+        src_o = y_o;
+    }
+    // M x = src: b^ = src_e + kappa D_eo R_oo^-1 src_o (sym: R_ee^-1 of it)   (e0)
+    TM_TRY(hop1(ctx, HopCall{g, TM_FP64, 0, 0, 1,
+                             pc == TM_PC_SYM ? TM_EPI_TWINV_X_PLUS_KD : TM_EPI_X_PLUS_KD, src_o, e0,
+                             src_e, kappa, nrhs, FIN_NONE, nullptr, nullptr}));
+    TM_TRY(solve_pc(ctx, g, x_e, e0, par, TM_SOLUTION_MAT, res, &status));
+    // x_o = R_oo^-1 (src_o + kappa D_oe x_e)
+    TM_TRY(hop1(ctx, HopCall{g, TM_FP64, 1, 0, 0, TM_EPI_TWINV_X_PLUS_KD, x_e, x_o, src_o, kappa, nrhs,
+                             FIN_NONE, nullptr, nullptr}));
+    // residual of the full system: v = M x (e1, o0); MATDAG_MAT: v = M^+ M x (e0, o1)
+    const void *ve = e1, *vo = o0;
+    TM_TRY(full_op64(ctx, g, e1, o0, x_e, x_o, 0, nrhs));
+    if (par->solution == TM_SOLUTION_MATDAG_MAT) {
+        void *o1 = solve_field(ctx, "o1", g, nrhs, &rc);
+        if (!o1) return rc;
+        TM_TRY(full_op64(ctx, g, e0, o1, e1, o0, 1, nrhs));
+        ve = e0;
+        vo = o1;
+    }
+    void *d = y_e ? y_e : solve_field(ctx, "d", g, nrhs, &rc);
+    if (!d) return rc;
+    std::vector<double> re, ro, be, bo;
+    TM_TRY(diff_norm2(ctx, g, b_e, ve, d, nrhs, re));
+    TM_TRY(diff_norm2(ctx, g, b_o, vo, d, nrhs, ro));
+    TM_TRY(diff_norm2(ctx, g, b_e, nullptr, d, nrhs, be));
+    TM_TRY(diff_norm2(ctx, g, b_o, nullptr, d, nrhs, bo));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < nrhs; i++) {
+        const double bb = be[i] + bo[i];
+        res[i].true_rel_res_full = bb > 0 ? std::sqrt((re[i] + ro[i]) / bb) : 0.0;
+        res[i].seconds = secs;
+        if (!std::isfinite(res[i].true_rel_res_full)) return fail(ctx, TM_ERR_NAN, "non-finite residual");
+    }
+    return status;
+}
+
 int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm_gauge *g,
              tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev)
 {
@@ -1427,7 +1626,8 @@ int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm
     if (!F_dev || !X_e) return fail(ctx, TM_ERR_ARG, "null pointer");
     if (pc != TM_PC_ASYM && pc != TM_PC_SYM) return fail(ctx, TM_ERR_ARG, "bad pc type");
     if (!std::isfinite(coeff)) return fail(ctx, TM_ERR_ARG, "non-finite coeff");
-    if (g->recon != 12 && g->recon != 18) return fail(ctx, TM_ERR_ARG, "bad recon");
+    if (g->recon != 12 && g->recon != 18)
+        return fail(ctx, TM_ERR_ARG, "the force kernel reads 12- or 18-real links");
     int rc = TM_OK;
     const size_t fb = spinor_field_bytes(prec, g->vh, g->nf, 1);
     void *Y = workspace(ctx, "force_y", fb, &rc);

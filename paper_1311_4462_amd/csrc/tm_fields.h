@@ -6,11 +6,11 @@
 namespace twm {
 
 hipError_t gauge_pack(int prec, int recon, void *dst0, void *dst1, const void *src, const int *X,
-                      uint32_t vh, hipStream_t st);
+                      uint32_t vh, int *bad, hipStream_t st);
 hipError_t spinor_pack(int prec, SpinorPtr dst, const void *src, const int *X, uint32_t vh, int par,
-                       int nf, int nrhs, hipStream_t st);
+                       int nf, int nrhs, int basis, hipStream_t st);
 hipError_t spinor_unpack(int prec, void *dst, SpinorPtr src, const int *X, uint32_t vh, int par,
-                         int nf, int nrhs, hipStream_t st);
+                         int nf, int nrhs, int basis, hipStream_t st);
 hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t vh, int nrhs,
                        Twist tw, int inverse, hipStream_t st);
 

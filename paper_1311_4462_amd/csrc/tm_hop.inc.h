@@ -492,6 +492,12 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
         TM_HOP_CASES(P, 2, 1, 12, 128)                                                         \
         TM_HOP_CASES(P, 2, 1, 12, 64)                                                          \
         TM_HOP_CASES(P, 2, 1, 18, 256)                                                         \
+        TM_HOP_CASES(P, 1, 1, 8, 256)                                                          \
+        TM_HOP_CASES(P, 1, 1, 8, 128)                                                          \
+        TM_HOP_CASES(P, 1, 1, 8, 64)                                                           \
+        TM_HOP_CASES(P, 2, 1, 8, 256)                                                          \
+        TM_HOP_CASES(P, 2, 1, 8, 128)                                                          \
+        TM_HOP_CASES(P, 2, 1, 8, 64)                                                           \
         if constexpr (P != TM_FP64) {                                                          \
             TM_HOP_CASES(P, 1, 4, 12, 256)                                                     \
             TM_HOP_CASES(P, 1, 4, 12, 128)                                                     \
@@ -501,6 +507,8 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
         TM_HOP_CASES_TWL(P, 1, 1, 18)                                                          \
         TM_HOP_CASES_TWL(P, 2, 1, 12)                                                          \
         TM_HOP_CASES_TWL(P, 2, 1, 18)                                                          \
+        TM_HOP_CASES_TWL(P, 1, 1, 8)                                                           \
+        TM_HOP_CASES_TWL(P, 2, 1, 8)                                                           \
         return hipErrorInvalidConfiguration;                                                   \
     }
 

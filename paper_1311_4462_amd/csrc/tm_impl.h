@@ -315,7 +315,7 @@ __host__ __device__ inline size_t link_elem_bytes(int prec)
 }
 __host__ __device__ inline size_t gauge_parity_bytes(int prec, int recon, long vh)
 {
-    size_t b = link_elem_bytes(prec) * (recon == 12 ? 6 : 9) * 4 * (size_t)vh;
+    size_t b = link_elem_bytes(prec) * (recon == 12 ? 6 : (recon == 8 ? 4 : 9)) * 4 * (size_t)vh;
     return (b + 255) & ~(size_t)255;
 }
 
@@ -323,12 +323,23 @@ __host__ __device__ inline size_t gauge_parity_bytes(int prec, int recon, long v
 //   FP64       NE rows of one complex (double2)
 //   FP32  12:  3 rows of two complex (float4)
 //   FP32  18:  4 rows of two complex (float4), then 1 row of one complex (float2)
+//   FP32   8:  2 rows of two complex (float4)
 //   half  12:  1 row of four complex (16 B), then 1 row of two complex (8 B)
 //   half  18:  2 rows of four complex (16 B), then 1 row of one complex (4 B)
+//   half   8:  1 row of four complex (16 B)
+// Stored elements, row-major: 12 -> rows 0 and 1; 18 -> all nine; 8 -> a2, a3,
+// b1 and (arg a1, arg c1) as the real and imaginary part of the fourth slot
+// (a, b, c the rows of the link).
 template <int P, int RECON, bool NT = true>
 struct LinkIO {
     using real = typename Prec<P>::real;
-    static constexpr int NE = (RECON == 12) ? 6 : 9;
+    // half-precision 8-real links: phase = k * pi / 32767, k a 16-bit integer
+    static constexpr double kPhaseStepD = 3.14159265358979323846 / 32767.0;
+    static constexpr real kPhaseStep = (real)kPhaseStepD;
+    static constexpr int NE = (RECON == 12) ? 6 : (RECON == 8 ? 4 : 9);
+    static constexpr int NR32 = NE / 2;         // FP32 16-byte rows (two complex each)
+    static constexpr int NR16 = NE / 4;         // half 16-byte rows (four complex each)
+    static constexpr int T16 = NE % 4;          // half tail: complex per site
 
     // start of the 16-byte row k, and of the narrow tail row
     __device__ static __forceinline__ const char *row16(const void *base, uint32_t vh, int mu, int k,
@@ -347,6 +358,46 @@ struct LinkIO {
         return mk(half_to_f<P>(c & 0xffff), half_to_f<P>(c >> 16));
     }
 
+    // 8-real links.  Unit norm of row a and of column 1 give |a1|^2 = 1 - N,
+    // N = |a2|^2 + |a3|^2, and |c1|^2 = N - |b1|^2.  Orthogonality of a to b
+    // and c, with b = conj(c x a) and c = conj(a x b) (det U = 1), leaves a
+    // 2x2 linear system for each of (b2, b3) and (c2, c3), of determinant N:
+    //   b2 = -(a3* c1* + a1* a2 b1) / N     b3 = (a2* c1* - a1* a3 b1) / N
+    //   c2 =  (a3* b1* - a1* a2 c1) / N     c3 = -(a2* b1* + a1* a3 c1) / N
+    // Links with N = 0 (a1 of modulus one) cannot be represented; the gauge
+    // upload rejects them.
+    __device__ static __forceinline__ void recon8(cx<real> (&u)[3][3], cx<real> a2, cx<real> a3,
+                                                  cx<real> b1, real tha, real thc)
+    {
+        const real n = a2.re * a2.re + a2.im * a2.im + a3.re * a3.re + a3.im * a3.im;
+        const real ra = sqrt(fmax(real(1) - n, real(0)));
+        const real rc = sqrt(fmax(n - (b1.re * b1.re + b1.im * b1.im), real(0)));
+        real sa, ca, sc, cc;
+        if constexpr (sizeof(real) == 8) {
+            sincos(tha, &sa, &ca);
+            sincos(thc, &sc, &cc);
+        } else {
+            // hardware sine / cosine: absolute error ~1e-6 on [-pi, pi]
+            __sincosf(tha, &sa, &ca);
+            __sincosf(thc, &sc, &cc);
+        }
+        const cx<real> a1 = mk(ra * ca, ra * sa), c1 = mk(rc * cc, rc * sc);
+        const real in = real(1) / n;
+        const cx<real> a2b1 = cjmul(a1, cmul(a2, b1)), a3b1 = cjmul(a1, cmul(a3, b1));
+        const cx<real> a2c1 = cjmul(a1, cmul(a2, c1)), a3c1 = cjmul(a1, cmul(a3, c1));
+        const cx<real> a3c1s = conjg(cmul(a3, c1)), a2c1s = conjg(cmul(a2, c1));
+        const cx<real> a3b1s = conjg(cmul(a3, b1)), a2b1s = conjg(cmul(a2, b1));
+        u[0][0] = a1;
+        u[0][1] = a2;
+        u[0][2] = a3;
+        u[1][0] = b1;
+        u[1][1] = (-in) * (a3c1s + a2b1);
+        u[1][2] = in * (a2c1s - a3b1);
+        u[2][0] = c1;
+        u[2][1] = in * (a3b1s - a2c1);
+        u[2][2] = (-in) * (a2b1s + a3c1);
+    }
+
     __device__ static __forceinline__ void load(cx<real> (&u)[3][3], const void *base, uint32_t vh,
                                                 int mu, uint32_t cb)
     {
@@ -359,79 +410,101 @@ struct LinkIO {
                 e[k] = mk(c.x, c.y);
             }
         } else if constexpr (P == TM_FP32) {
-            constexpr int NR = (RECON == 12) ? 3 : 4;
 #pragma unroll
-            for (int k = 0; k < NR; k++) {
-                float4 c = ldl<NT>(at<float4>(row16(base, vh, mu, k, NR), o16));
+            for (int k = 0; k < NR32; k++) {
+                float4 c = ldl<NT>(at<float4>(row16(base, vh, mu, k, NR32), o16));
                 e[2 * k] = mk(c.x, c.y);
                 e[2 * k + 1] = mk(c.z, c.w);
             }
-            if constexpr (RECON == 18) {
-                float2 c = ldl<NT>(at<float2>(tail(base, vh, mu, 4, 8), cb * 8u));
-                e[8] = mk(c.x, c.y);
+            if constexpr (NE % 2 == 1) {
+                float2 c = ldl<NT>(at<float2>(tail(base, vh, mu, NR32, 8), cb * 8u));
+                e[NE - 1] = mk(c.x, c.y);
             }
         } else {
-            constexpr int NR = (RECON == 12) ? 1 : 2;
 #pragma unroll
-            for (int k = 0; k < NR; k++) {
-                uint4 c = ldl<NT>(at<uint4>(row16(base, vh, mu, k, NR), o16));
+            for (int k = 0; k < NR16; k++) {
+                uint4 c = ldl<NT>(at<uint4>(row16(base, vh, mu, k, NR16), o16));
                 e[4 * k] = h2c(c.x);
                 e[4 * k + 1] = h2c(c.y);
                 e[4 * k + 2] = h2c(c.z);
-                e[4 * k + 3] = h2c(c.w);
+                if constexpr (RECON == 8)
+                    e[3] = mk(kPhaseStep * (real)(int16_t)(c.w & 0xffff), kPhaseStep * (real)(int16_t)(c.w >> 16));
+                else
+                    e[4 * k + 3] = h2c(c.w);
             }
-            if constexpr (RECON == 12) {
-                uint2 c = ldl<NT>(at<uint2>(tail(base, vh, mu, 1, 8), cb * 8u));
-                e[4] = h2c(c.x);
-                e[5] = h2c(c.y);
-            } else {
-                uint32_t c = ldl<NT>(at<uint32_t>(tail(base, vh, mu, 2, 4), cb * 4u));
-                e[8] = h2c(c);
+            if constexpr (T16 == 2) {
+                uint2 c = ldl<NT>(at<uint2>(tail(base, vh, mu, NR16, 8), cb * 8u));
+                e[4 * NR16] = h2c(c.x);
+                e[4 * NR16 + 1] = h2c(c.y);
+            } else if constexpr (T16 == 1) {
+                uint32_t c = ldl<NT>(at<uint32_t>(tail(base, vh, mu, NR16, 4), cb * 4u));
+                e[4 * NR16] = h2c(c);
             }
         }
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int b = 0; b < 3; b++) u[a][b] = e[3 * a + b];
-        if constexpr (RECON == 12) {
-            // third row of an SU(3) matrix: conj(row0 x row1)
-            u[2][0] = conjg(cmul(u[0][1], u[1][2]) - cmul(u[0][2], u[1][1]));
-            u[2][1] = conjg(cmul(u[0][2], u[1][0]) - cmul(u[0][0], u[1][2]));
-            u[2][2] = conjg(cmul(u[0][0], u[1][1]) - cmul(u[0][1], u[1][0]));
+        if constexpr (RECON == 8) {
+            recon8(u, e[0], e[1], e[2], e[3].re, e[3].im);
         } else {
 #pragma unroll
-            for (int b = 0; b < 3; b++) u[2][b] = e[6 + b];
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 3; b++) u[a][b] = e[3 * a + b];
+            if constexpr (RECON == 12) {
+                // third row of an SU(3) matrix: conj(row0 x row1)
+                u[2][0] = conjg(cmul(u[0][1], u[1][2]) - cmul(u[0][2], u[1][1]));
+                u[2][1] = conjg(cmul(u[0][2], u[1][0]) - cmul(u[0][0], u[1][2]));
+                u[2][2] = conjg(cmul(u[0][0], u[1][1]) - cmul(u[0][1], u[1][0]));
+            } else {
+#pragma unroll
+                for (int b = 0; b < 3; b++) u[2][b] = e[6 + b];
+            }
         }
     }
 
-    // Write the stored elements (row-major, NE complex) of one link.
+    // Write the stored elements of one link given in full (row-major, nine
+    // complex, FP64).
     __device__ static __forceinline__ void store(void *base, uint32_t vh, int mu, uint32_t cb,
-                                                 const double2 *e)
+                                                 const double2 *full)
     {
+        double2 e[9];
+        if constexpr (RECON == 8) {
+            e[0] = full[1];
+            e[1] = full[2];
+            e[2] = full[3];
+            e[3] = make_double2(atan2(full[0].y, full[0].x), atan2(full[6].y, full[6].x));
+        } else {
+            for (int k = 0; k < NE; k++) e[k] = full[k];
+        }
         char *b = (char *)base;
         const uint32_t o16 = cb * 16u;
         if constexpr (P == TM_FP64) {
             for (int k = 0; k < NE; k++)
                 *at_w<double2>((void *)row16(b, vh, mu, k, NE), o16) = e[k];
         } else if constexpr (P == TM_FP32) {
-            constexpr int NR = (RECON == 12) ? 3 : 4;
-            for (int k = 0; k < NR; k++)
-                *at_w<float4>((void *)row16(b, vh, mu, k, NR), o16) =
+            for (int k = 0; k < NR32; k++)
+                *at_w<float4>((void *)row16(b, vh, mu, k, NR32), o16) =
                     make_float4((float)e[2 * k].x, (float)e[2 * k].y, (float)e[2 * k + 1].x, (float)e[2 * k + 1].y);
-            if constexpr (RECON == 18)
-                *at_w<float2>((void *)tail(b, vh, mu, 4, 8), cb * 8u) = make_float2((float)e[8].x, (float)e[8].y);
+            if constexpr (NE % 2 == 1)
+                *at_w<float2>((void *)tail(b, vh, mu, NR32, 8), cb * 8u) =
+                    make_float2((float)e[NE - 1].x, (float)e[NE - 1].y);
         } else {
             auto c2h = [](double2 v) {
                 return (uint32_t)f_to_half<P>((float)v.x) | ((uint32_t)f_to_half<P>((float)v.y) << 16);
             };
-            constexpr int NR = (RECON == 12) ? 1 : 2;
-            for (int k = 0; k < NR; k++)
-                *at_w<uint4>((void *)row16(b, vh, mu, k, NR), o16) =
-                    make_uint4(c2h(e[4 * k]), c2h(e[4 * k + 1]), c2h(e[4 * k + 2]), c2h(e[4 * k + 3]));
-            if constexpr (RECON == 12)
-                *at_w<uint2>((void *)tail(b, vh, mu, 1, 8), cb * 8u) = make_uint2(c2h(e[4]), c2h(e[5]));
-            else
-                *at_w<uint32_t>((void *)tail(b, vh, mu, 2, 4), cb * 4u) = c2h(e[8]);
+            // 16-bit fixed-point phases: a float16 / bfloat16 angle near pi
+            // would carry an error of up to 2e-3 / 8e-3 rad
+            auto ph = [](double2 v) {
+                auto q = [](double t) { return (uint32_t)(uint16_t)(int16_t)__double2int_rn(t / kPhaseStepD); };
+                return q(v.x) | (q(v.y) << 16);
+            };
+            for (int k = 0; k < NR16; k++)
+                *at_w<uint4>((void *)row16(b, vh, mu, k, NR16), o16) =
+                    make_uint4(c2h(e[4 * k]), c2h(e[4 * k + 1]), c2h(e[4 * k + 2]),
+                               RECON == 8 ? ph(e[3]) : c2h(e[4 * k + 3]));
+            if constexpr (T16 == 2)
+                *at_w<uint2>((void *)tail(b, vh, mu, NR16, 8), cb * 8u) =
+                    make_uint2(c2h(e[4 * NR16]), c2h(e[4 * NR16 + 1]));
+            else if constexpr (T16 == 1)
+                *at_w<uint32_t>((void *)tail(b, vh, mu, NR16, 4), cb * 4u) = c2h(e[4 * NR16]);
         }
     }
 };
