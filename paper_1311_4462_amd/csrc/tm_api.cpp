@@ -214,20 +214,32 @@ int choose_nr(int prec, int nf, int nrhs, int recon)
 // block size, and whether links are loaded non-temporally (bypassing the
 // caches: best when the working set exceeds the 256 MB last-level cache) or
 // ordinarily (they can then stay cache resident across launches).
+// wcap > 0 caps the resident waves per SIMD at about wcap by giving each
+// block an otherwise unused share of the 160 KiB of LDS of a compute unit:
+// fewer waves in flight keep more of the neighbour spinors they share in L2.
 struct HopCfg {
     int bs;
     bool lnt;
+    int wcap;
 };
+constexpr unsigned kLdsPerCU = 160u << 10;
+unsigned hop_lds_bytes(const HopCfg &c)
+{
+    if (c.wcap <= 0) return 0;
+    const unsigned blocks = std::max(1u, (unsigned)(4 * c.wcap * 64 / c.bs));   // per compute unit
+    return ((kLdsPerCU / blocks) + 511u) & ~511u;
+}
 std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon)
 {
-    if (twl) return {{256, true}};
+    if (twl) return {{256, true, 0}};
     std::vector<int> bss = (recon == 18) ? std::vector<int>{256}
                            : (nr == 1) ? std::vector<int>{64, 128, 256} : std::vector<int>{128, 256};
     std::vector<HopCfg> out;
-    for (int b : bss) {
-        out.push_back({b, true});
-        out.push_back({b, false});
-    }
+    for (int b : bss)
+        for (int w : {0, 4, 3, 2}) {
+            out.push_back({b, true, w});
+            out.push_back({b, false, w});
+        }
     return out;
 }
 
@@ -235,8 +247,8 @@ std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon)
 // links and three spinor fields fit well inside the last-level cache.
 HopCfg default_cfg(int twl, size_t working_set)
 {
-    if (twl) return {256, true};
-    return {256, working_set > (size_t)200 << 20};
+    if (twl) return {256, true, 0};
+    return {256, working_set > (size_t)200 << 20, 0};
 }
 
 std::string tune_key(int prec, int nf, int nr, int dagger, int twl, int epi, int recon, long vh_total)
@@ -271,13 +283,14 @@ void load_tune(tm_ctx *ctx)
 }
 
 hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger, int twl, int recon,
-                        int bs, bool lnt, hipStream_t st)
+                        const HopCfg &c, hipStream_t st)
 {
+    const unsigned lds = hop_lds_bytes(c);
     switch (prec) {
-    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
-    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
-    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
-    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, bs, lnt, st);
+    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
+    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
+    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
+    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
     }
     return hipErrorInvalidValue;
 }
@@ -374,11 +387,12 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     const std::string key = tune_key(prec, nf, nr, dagger, twl, calls[0].epi, recon, vh_total);
     auto it = ctx->tuned.find(key);
     if (ctx->force_bs || ctx->force_lnt >= 0) {
-        HopCfg want{ctx->force_bs ? ctx->force_bs : cfg.bs, ctx->force_lnt >= 0 ? ctx->force_lnt != 0 : cfg.lnt};
+        HopCfg want{ctx->force_bs ? ctx->force_bs : cfg.bs, ctx->force_lnt >= 0 ? ctx->force_lnt != 0 : cfg.lnt,
+                    0};
         for (const HopCfg &c : cand)
-            if (c.bs == want.bs && c.lnt == want.lnt) cfg = want;
+            if (c.bs == want.bs && c.lnt == want.lnt && c.wcap == 0) cfg = want;
     } else if (it != ctx->tuned.end()) {
-        cfg = HopCfg{it->second & 0xffff, (it->second >> 16) != 0};
+        cfg = HopCfg{it->second & 0xffff, ((it->second >> 16) & 1) != 0, it->second >> 20};
     } else if (ctx->tuning && cand.size() > 1) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(ctx->stream, &cs);
@@ -392,10 +406,10 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             for (const HopCfg &c : cand) {
                 HopBatch B;
                 TM_TRY(build_hop_batch(ctx, calls, n, nr, c.bs, &B));
-                TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c.bs, c.lnt, ctx->stream));
+                TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
                 for (int r = 0; r < 4; r++)
-                    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c.bs, c.lnt, ctx->stream));
+                    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e1, ctx->stream));
                 TM_HIP(ctx, hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -407,14 +421,14 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0);
+            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0) | (cfg.wcap << 20);
             ctx->tuned[key] = code;
             save_tune(ctx, key, code);
         }
     }
     HopBatch B;
     TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B));
-    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg.bs, cfg.lnt, ctx->stream));
+    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg, ctx->stream));
     TM_TRY(finish_reductions(ctx, B.p, n));
     return TM_OK;
 }

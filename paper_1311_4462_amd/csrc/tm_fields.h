@@ -16,7 +16,7 @@ hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t v
 
 template <int P>
 hipError_t launch_hop_prec(const HopBatch &B, int nf, int nr, int dagger, int twl, int recon,
-                           int bs, bool lnt, hipStream_t st);
+                           int bs, bool lnt, unsigned lds, hipStream_t st);
 
 // ---------------------------------------------------------------- BLAS
 

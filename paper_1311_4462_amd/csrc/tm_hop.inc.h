@@ -15,9 +15,64 @@
 
 namespace twm {
 
+// acc += k f g with k = +1 (K = 0), -1 (K = 1), +i (K = 2) or -i (K = 3):
+// two FMAs.
+template <int K, typename T>
+__device__ __forceinline__ void acc_k(cx<T> &acc, T f, cx<T> g)
+{
+    if constexpr (K == 0) {
+        acc.re = fma(f, g.re, acc.re);
+        acc.im = fma(f, g.im, acc.im);
+    } else if constexpr (K == 1) {
+        acc.re = fma(-f, g.re, acc.re);
+        acc.im = fma(-f, g.im, acc.im);
+    } else if constexpr (K == 2) {
+        acc.re = fma(-f, g.im, acc.re);
+        acc.im = fma(f, g.re, acc.im);
+    } else {
+        acc.re = fma(f, g.im, acc.re);
+        acc.im = fma(-f, g.re, acc.im);
+    }
+}
+
+// Row a of U h (BWD: of U^+ h) as two FMA chains of six terms.
+template <bool BWD, typename T>
+__device__ __forceinline__ cx<T> link_row(const cx<T> (&u)[3][3], const cx<T> (&h)[3], int a)
+{
+    T re, im;
+    if constexpr (!BWD) {
+        re = u[a][0].re * h[0].re;
+        re = fma(-u[a][0].im, h[0].im, re);
+        im = u[a][0].re * h[0].im;
+        im = fma(u[a][0].im, h[0].re, im);
+#pragma unroll
+        for (int b = 1; b < 3; b++) {
+            re = fma(u[a][b].re, h[b].re, re);
+            re = fma(-u[a][b].im, h[b].im, re);
+            im = fma(u[a][b].re, h[b].im, im);
+            im = fma(u[a][b].im, h[b].re, im);
+        }
+    } else {
+        re = u[0][a].re * h[0].re;
+        re = fma(u[0][a].im, h[0].im, re);
+        im = u[0][a].re * h[0].im;
+        im = fma(-u[0][a].im, h[0].re, im);
+#pragma unroll
+        for (int b = 1; b < 3; b++) {
+            re = fma(u[b][a].re, h[b].re, re);
+            re = fma(u[b][a].im, h[b].im, re);
+            im = fma(u[b][a].re, h[b].im, im);
+            im = fma(-u[b][a].im, h[b].re, im);
+        }
+    }
+    return mk(re, im);
+}
+
 // Project, multiply by the link and accumulate one hop.
 //   SIG = +1: projector (1 - g_mu);  SIG = -1: projector (1 + g_mu)
 //   BWD: use U^+ (backward hop) instead of U.
+// The link products are FMA chains and the hop's factor (boundary sign,
+// and 2 for the time projector) enters through the accumulating FMAs.
 template <int MU, int SIG, bool BWD, typename T>
 __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u)[3][3],
                                                const cx<T> *v, T sgn)
@@ -57,61 +112,31 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
         }
     }
     const T f = (MU == 3) ? (T)2 * sgn : sgn;
-    cx<T> g[2][3];
-#pragma unroll
-    for (int s = 0; s < 2; s++)
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            cx<T> t;
-            if constexpr (!BWD) {
-                t = cmul(u[a][0], h[s][0]);
-                t = t + cmul(u[a][1], h[s][1]);
-                t = t + cmul(u[a][2], h[s][2]);
-            } else {
-                t = cjmul(u[0][a], h[s][0]);
-                t = t + cjmul(u[1][a], h[s][1]);
-                t = t + cjmul(u[2][a], h[s][2]);
-            }
-            g[s][a] = f * t;
-        }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
+        const cx<T> g0 = link_row<BWD>(u, h[0], c);
+        const cx<T> g1 = link_row<BWD>(u, h[1], c);
         if constexpr (MU == 3) {
             if constexpr (SIG > 0) {
-                acc[6 + c] = acc[6 + c] + g[0][c];
-                acc[9 + c] = acc[9 + c] + g[1][c];
+                acc_k<0>(acc[6 + c], f, g0);
+                acc_k<0>(acc[9 + c], f, g1);
             } else {
-                acc[c] = acc[c] + g[0][c];
-                acc[3 + c] = acc[3 + c] + g[1][c];
+                acc_k<0>(acc[c], f, g0);
+                acc_k<0>(acc[3 + c], f, g1);
             }
         } else {
-            acc[c] = acc[c] + g[0][c];
-            acc[3 + c] = acc[3 + c] + g[1][c];
+            acc_k<0>(acc[c], f, g0);
+            acc_k<0>(acc[3 + c], f, g1);
             // lower pair: SIG * i s_k g
             if constexpr (MU == 0) {          // (i g1, i g0)
-                if constexpr (SIG > 0) {
-                    acc[6 + c] = acc[6 + c] + times_i(g[1][c]);
-                    acc[9 + c] = acc[9 + c] + times_i(g[0][c]);
-                } else {
-                    acc[6 + c] = acc[6 + c] + times_mi(g[1][c]);
-                    acc[9 + c] = acc[9 + c] + times_mi(g[0][c]);
-                }
+                acc_k<(SIG > 0 ? 2 : 3)>(acc[6 + c], f, g1);
+                acc_k<(SIG > 0 ? 2 : 3)>(acc[9 + c], f, g0);
             } else if constexpr (MU == 1) {   // (g1, -g0)
-                if constexpr (SIG > 0) {
-                    acc[6 + c] = acc[6 + c] + g[1][c];
-                    acc[9 + c] = acc[9 + c] - g[0][c];
-                } else {
-                    acc[6 + c] = acc[6 + c] - g[1][c];
-                    acc[9 + c] = acc[9 + c] + g[0][c];
-                }
+                acc_k<(SIG > 0 ? 0 : 1)>(acc[6 + c], f, g1);
+                acc_k<(SIG > 0 ? 1 : 0)>(acc[9 + c], f, g0);
             } else {                          // (i g0, -i g1)
-                if constexpr (SIG > 0) {
-                    acc[6 + c] = acc[6 + c] + times_i(g[0][c]);
-                    acc[9 + c] = acc[9 + c] + times_mi(g[1][c]);
-                } else {
-                    acc[6 + c] = acc[6 + c] + times_mi(g[0][c]);
-                    acc[9 + c] = acc[9 + c] + times_i(g[1][c]);
-                }
+                acc_k<(SIG > 0 ? 2 : 3)>(acc[6 + c], f, g0);
+                acc_k<(SIG > 0 ? 3 : 2)>(acc[9 + c], f, g1);
             }
         }
     }
@@ -463,7 +488,7 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
     if (nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON && lnt == LNT &&      \
         bs == BS) {                                                                                 \
         hipLaunchKernelGGL((hop_kernel<P, NF, NR, DAG, TWL, RECON, LNT, BS>), dim3(B.total_blocks), \
-                           dim3(BS), 0, st, B);                                                     \
+                           dim3(BS), lds, st, B);                                                   \
         return hipGetLastError();                                                                   \
     }
 
@@ -482,7 +507,7 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
 #define TM_HOP_DEFINE(P)                                                                       \
     template <>                                                                                \
     hipError_t launch_hop_prec<P>(const HopBatch &B, int nf, int nr, int dagger, int twl,      \
-                                  int recon, int bs, bool lnt, hipStream_t st)                 \
+                                  int recon, int bs, bool lnt, unsigned lds, hipStream_t st)   \
     {                                                                                          \
         TM_HOP_CASES(P, 1, 1, 12, 256)                                                         \
         TM_HOP_CASES(P, 1, 1, 12, 128)                                                         \
