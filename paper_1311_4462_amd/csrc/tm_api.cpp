@@ -437,6 +437,12 @@ int hop1(tm_ctx *ctx, const HopCall &c) { return launch_hops(ctx, &c, 1); }
 
 // ------------------------------------------------------------------ BLAS launch
 
+constexpr size_t kBlasMaxBlocks = 4096;   // blocks per rhs of a BLAS launch
+#ifndef TM_BLAS_UNROLL
+#define TM_BLAS_UNROLL 4
+#endif
+constexpr size_t kBlasUnroll = TM_BLAS_UNROLL;   // units per thread and pass (streaming path)
+
 struct BlasCall {
     uint32_t vh;
     int nrhs;
@@ -461,7 +467,12 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         bp.vh = c.vh;
         bp.nrhs = c.nrhs;
         bp.blk_start = blocks;
-        bp.nblk = (int)std::min<uint32_t>((c.vh + 255) / 256, 1024u);
+        // units one rhs streams: chunks when every operand is FP64 / FP32
+        // (one complex when both are FP64, else two), sites otherwise
+        const bool flat = pa <= TM_FP32 && pb <= TM_FP32;
+        const size_t units = flat ? (size_t)nf * ((pa == TM_FP64 && pb == TM_FP64) ? 12 : 6) * c.vh : c.vh;
+        const size_t per_block = flat ? 256 * kBlasUnroll : 256;
+        bp.nblk = (int)std::min<size_t>((units + per_block - 1) / per_block, kBlasMaxBlocks);
         // vector precisions per operation (see BlasOp)
         int vp[4] = {pa, pa, pa, pa};
         switch (op) {
@@ -1038,8 +1049,10 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     // reduction slots at their largest size and the odd temporaries.
     for (int i = 0; i < n; i++) {
         RedSlot rs;
-        const size_t need = std::max<size_t>(((pr[i].g->vh + 127) / 128) * pr[i].nrhs,
-                                             (size_t)2048 * pr[i].nrhs);
+        // hop partials (one per 64-site block at most) and BLAS partials
+        // (up to kBlasMaxBlocks per rhs, two per block for a dot product)
+        const size_t need = std::max<size_t>(((pr[i].g->vh + 63) / 64) * pr[i].nrhs,
+                                             (size_t)2 * kBlasMaxBlocks * pr[i].nrhs);
         TM_TRY(red_slot(ctx, i, need, &rs));
         int rc = TM_OK;
         if (!odd_tmp(ctx, i, pr[i].g, TM_FP64, pr[i].nrhs, &rc)) return rc;

@@ -36,6 +36,72 @@ __device__ __forceinline__ double nrm2_12(const cx<double> (&v)[12])
     return s;
 }
 
+// FP64 / FP32 fields are flat arrays of 16-byte chunks, [rhs][flavour][row][cb]
+// with rows of vh chunks, so element-wise operations stream them chunk by
+// chunk: a unit is U complex numbers (U = 1 when every operand is FP64, else
+// 2 = one FP32 chunk = two FP64 chunks of rows 2j, 2j+1), u counts the units
+// of one rhs and cb = u mod vh.
+template <int P, int U>
+__device__ __forceinline__ void unit_load(cx<double> (&v)[U], const SpinorPtr &s, size_t rbase, size_t u,
+                                          uint32_t cb, uint32_t vh)
+{
+    if constexpr (P == TM_FP64) {
+        const double2 *d = (const double2 *)s.data + rbase;
+        if constexpr (U == 1) {
+            const double2 a = d[u];
+            v[0] = mk(a.x, a.y);
+        } else {
+            const size_t i0 = 2 * u - cb;
+            const double2 a = d[i0], b = d[i0 + vh];
+            v[0] = mk(a.x, a.y);
+            v[1] = mk(b.x, b.y);
+        }
+    } else {
+        const float4 a = ((const float4 *)s.data)[rbase + u];
+        v[0] = mk((double)a.x, (double)a.y);
+        v[1] = mk((double)a.z, (double)a.w);
+    }
+}
+
+template <int P, int U>
+__device__ __forceinline__ void unit_store(const SpinorPtr &s, size_t rbase, size_t u, uint32_t cb,
+                                           uint32_t vh, const cx<double> (&v)[U])
+{
+    if constexpr (P == TM_FP64) {
+        double2 *d = (double2 *)s.data + rbase;
+        if constexpr (U == 1) {
+            d[u] = make_double2(v[0].re, v[0].im);
+        } else {
+            const size_t i0 = 2 * u - cb;
+            d[i0] = make_double2(v[0].re, v[0].im);
+            d[i0 + vh] = make_double2(v[1].re, v[1].im);
+        }
+    } else {
+        ((float4 *)s.data)[rbase + u] =
+            make_float4((float)v[0].re, (float)v[0].im, (float)v[1].re, (float)v[1].im);
+    }
+}
+
+template <int U>
+__device__ __forceinline__ double unit_nrm2(const cx<double> (&v)[U])
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < U; k++) s += v[k].re * v[k].re + v[k].im * v[k].im;
+    return s;
+}
+
+#ifndef TM_BLAS_UNROLL
+#define TM_BLAS_UNROLL 4
+#endif
+
+// the chunk-streaming path serves operations whose operands are all FP64 / FP32
+template <int PA, int PB>
+constexpr bool blas_flat()
+{
+    return (PA == TM_FP64 || PA == TM_FP32) && (PB == TM_FP64 || PB == TM_FP32);
+}
+
 template <int OP, int PA, int PB, int BS>
 __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 {
@@ -58,6 +124,95 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
     if constexpr (OP == OP_CG_UPDATE) alpha = pb.red.cg[rhs].alpha;
     if constexpr (OP == OP_XPAY) beta = pb.red.cg[rhs].beta;
 
+    if constexpr (blas_flat<PA, PB>()) {
+        constexpr int U = (PA == TM_FP64 && PB == TM_FP64) ? 1 : 2;
+        const size_t units = (size_t)nf * (12 / U) * vh;
+        // chunk offsets of this rhs in each operand (FP64: 12 rows, FP32: 6)
+        const size_t ra = (size_t)rhs * nf * (PA == TM_FP64 ? 12 : 6) * vh;
+        const size_t rb = (size_t)rhs * nf * (PB == TM_FP64 ? 12 : 6) * vh;
+        // TM_BLAS_UNROLL units per thread and pass, their loads issued together
+        constexpr int UN = TM_BLAS_UNROLL;
+        const size_t stride = (size_t)pb.nblk * BS * UN;
+        for (size_t u0 = (size_t)blk * BS * UN + threadIdx.x; u0 < units; u0 += stride) {
+            cx<double> a0[UN][U], a1[UN][U], a2[UN][U], a3[UN][U];
+            uint32_t cbs[UN];
+            bool ok[UN];
+#pragma unroll
+            for (int q = 0; q < UN; q++) {
+                const size_t u = u0 + (size_t)q * BS;
+                ok[q] = u < units;
+                cbs[q] = (uint32_t)(u % vh);
+                if (!ok[q]) continue;
+                if constexpr (OP == OP_CG_UPDATE) {
+                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
+                    unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
+                    unit_load<PB, U>(a2[q], pb.v[2], rb, u, cbs[q], vh);
+                    unit_load<PB, U>(a3[q], pb.v[3], rb, u, cbs[q], vh);
+                } else if constexpr (OP == OP_XPAY) {
+                    unit_load<PB, U>(a0[q], pb.v[0], rb, u, cbs[q], vh);
+                    unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
+                } else if constexpr (OP == OP_RESIDUAL) {
+                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
+                    if (pb.v[1].data) unit_load<PA, U>(a1[q], pb.v[1], ra, u, cbs[q], vh);
+                } else if constexpr (OP == OP_CONVERT || OP == OP_NORM2) {
+                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
+                } else if constexpr (OP == OP_ACCUM_ZERO) {
+                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
+                    unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
+                } else if constexpr (OP == OP_DOT) {
+                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
+                    unit_load<PA, U>(a1[q], pb.v[1], ra, u, cbs[q], vh);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < UN; q++) {
+                if (!ok[q]) continue;
+                const size_t u = u0 + (size_t)q * BS;
+                const uint32_t cb = cbs[q];
+                if constexpr (OP == OP_CG_UPDATE) {          // x += alpha p, r -= alpha Ap, |r|^2
+#pragma unroll
+                    for (int k = 0; k < U; k++) {
+                        a0[q][k] = a0[q][k] + alpha * a1[q][k];
+                        a2[q][k] = a2[q][k] - alpha * a3[q][k];
+                    }
+                    unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
+                    unit_store<PB, U>(pb.v[2], rb, u, cb, vh, a2[q]);
+                    acc0 += unit_nrm2<U>(a2[q]);
+                } else if constexpr (OP == OP_XPAY) {        // p = r + beta p
+#pragma unroll
+                    for (int k = 0; k < U; k++) a1[q][k] = a0[q][k] + beta * a1[q][k];
+                    unit_store<PB, U>(pb.v[1], rb, u, cb, vh, a1[q]);
+                } else if constexpr (OP == OP_RESIDUAL) {    // r = c - y, |r|^2
+                    if (pb.v[1].data) {
+#pragma unroll
+                        for (int k = 0; k < U; k++) a0[q][k] = a0[q][k] - a1[q][k];
+                    }
+                    acc0 += unit_nrm2<U>(a0[q]);
+                    unit_store<PB, U>(pb.v[2], rb, u, cb, vh, a0[q]);
+                    if (pb.v[3].data) unit_store<PB, U>(pb.v[3], rb, u, cb, vh, a0[q]);
+                } else if constexpr (OP == OP_CONVERT) {
+                    unit_store<PB, U>(pb.v[1], rb, u, cb, vh, a0[q]);
+                } else if constexpr (OP == OP_ACCUM_ZERO) {  // y += x, x = 0
+#pragma unroll
+                    for (int k = 0; k < U; k++) {
+                        a0[q][k] = a0[q][k] + a1[q][k];
+                        a1[q][k] = mk(0.0, 0.0);
+                    }
+                    unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
+                    unit_store<PB, U>(pb.v[1], rb, u, cb, vh, a1[q]);
+                } else if constexpr (OP == OP_NORM2) {
+                    acc0 += unit_nrm2<U>(a0[q]);
+                } else if constexpr (OP == OP_DOT) {
+#pragma unroll
+                    for (int k = 0; k < U; k++) {
+                        const cx<double> t = cjmul(a0[q][k], a1[q][k]);
+                        acc0 += t.re;
+                        acc1 += t.im;
+                    }
+                }
+            }
+        }
+    } else
     for (uint32_t cb = blk * BS + threadIdx.x; cb < vh; cb += pb.nblk * BS) {
         for (int f = 0; f < nf; f++) {
             const uint32_t vec = rhs * nf + f;
