@@ -31,6 +31,9 @@ the design notes):
     right-preconditioned variable R_ee psi_e.
   * CG: conjugate gradient on the normal equations M^+ M x = M^+ b (the
     NORMOP solve of Sec. 2.2) in FP64, stopped on the true residual.
+  * Twisted clover (the future work of Sec. 4): R(x) = A(x) + i a g5 t3 + b t1
+    with A = 1 + i kappa c_sw sum_{mu<nu} sigma_munu F_munu, F from the
+    four-leaf clover (with_clover); every operator above then uses it.
 """
 from __future__ import annotations
 
@@ -107,6 +110,11 @@ class Params:
     eps: float = 0.0
     flavor: int = PLUS
     tsign: float = -1.0   # -1: antiperiodic in t
+    # twisted clover (see with_clover): c_sw and the per-site R, R^-1 on
+    # (flavour, spin, colour), shape [Lt, Lz, Ly, Lx, 12 nf, 12 nf]
+    csw: float = 0.0
+    clover_R: object = None
+    clover_Rinv: object = None
 
     @property
     def nf(self) -> int:
@@ -160,8 +168,17 @@ def project(psi: np.ndarray, dims, parity: int) -> np.ndarray:
 
 
 def twist(p: Params, psi: np.ndarray, inverse=False, dagger=False, parity: int = -1):
-    """R psi, R^-1 psi, R^+ psi or R^-+ psi on every site (parity -1) or one parity."""
-    out = _site_apply(twist_matrix(p, inverse, dagger), psi)
+    """R psi, R^-1 psi, R^+ psi or R^-+ psi on every site (parity -1) or one parity.
+    With a clover term attached (with_clover) R is the per-site matrix."""
+    if p.clover_R is not None:
+        m = p.clover_Rinv if inverse else p.clover_R
+        if dagger:
+            m = np.conj(np.swapaxes(m, -1, -2))
+        sh = psi.shape
+        v = psi.reshape(sh[:-3] + (sh[-3] * 12,))
+        out = np.einsum("...ij,...j->...i", m, v).reshape(sh)
+    else:
+        out = _site_apply(twist_matrix(p, inverse, dagger), psi)
     return out if parity < 0 else project(out, p.dims, parity)
 
 
@@ -277,6 +294,69 @@ def solve(p: Params, U, b, pc="asym", tol=1e-12, maxiter=10000):
     rhs = prepare(p, U, b, pc)
     x_e, info = cg(p, U, rhs, pc, tol, maxiter)
     return x_e + reconstruct(p, U, x_e, b), info
+
+
+# --- twisted clover (the paper's stated future work, Sec. 4) ------------------
+#
+# M = R - kappa D with R(x) = A(x) + i a g5 t3 + b t1 and the clover term
+#     A(x) = 1 + i kappa c_sw sum_{mu<nu} sigma_munu F_munu(x),
+#     sigma_munu = (i/2)[g_mu, g_nu],  F_munu = (Q_munu - Q_munu^+) / 8,
+# Q_munu(x) the sum of the four plaquettes of the mu-nu plane that start and
+# end at x (counter-clockwise).  c_sw = 0 gives back the twisted-mass R.
+
+def _nbr(f, mu, d):
+    """f(x + d mu^) for a field [Lt, Lz, Ly, Lx, ...]."""
+    return np.roll(f, -d, axis=3 - mu)
+
+
+def _dag(m):
+    return np.conj(np.swapaxes(m, -1, -2))
+
+
+def clover_leaves(U, mu, nu):
+    """Q_munu(x): the four plaquette leaves of the mu-nu plane at every site."""
+    Um, Un = U[mu], U[nu]
+    mm = lambda *ms: ms[0] if len(ms) == 1 else ms[0] @ mm(*ms[1:])
+    l1 = mm(Um, _nbr(Un, mu, 1), _dag(_nbr(Um, nu, 1)), _dag(Un))
+    Um_b = _nbr(Um, mu, -1)                       # U_mu(x - mu)
+    l2 = mm(Un, _dag(_nbr(Um_b, nu, 1)), _dag(_nbr(Un, mu, -1)), Um_b)
+    Un_b = _nbr(Un, nu, -1)                       # U_nu(x - nu)
+    l3 = mm(_dag(Um_b), _dag(_nbr(Un_b, mu, -1)), _nbr(Um_b, nu, -1), Un_b)
+    l4 = mm(_dag(Un_b), _nbr(Um, nu, -1), _nbr(Un_b, mu, 1), _dag(Um))
+    return l1 + l2 + l3 + l4
+
+
+def clover_term(p: Params, U, csw):
+    """A(x) on (spin, colour), shape [Lt, Lz, Ly, Lx, 12, 12]."""
+    g = gammas()
+    sh = U.shape[1:5]
+    A = np.zeros(sh + (12, 12), dtype=np.complex128)
+    A[...] = np.eye(12)
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            sig = 0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu])
+            Q = clover_leaves(U, mu, nu)
+            F = (Q - _dag(Q)) / 8.0
+            # kron(sigma, F) per site
+            A += 1j * p.kappa * csw * np.einsum("ab,...cd->...acbd", sig, F).reshape(sh + (12, 12))
+    return A
+
+
+def with_clover(p: Params, U, csw):
+    """A copy of p whose twist is the twisted-clover R(x) (and R^-1 by inversion)."""
+    from dataclasses import replace
+    A = clover_term(p, U, csw)
+    nf = p.nf
+    sh = A.shape[:4]
+    R = np.zeros(sh + (12 * nf, 12 * nf), dtype=np.complex128)
+    tw = twist_matrix(p)                      # 1 + i a g5 t3 + b t1 on (flavour, spin)
+    for f in range(nf):
+        for h in range(nf):
+            blk = np.kron(tw[4 * f:4 * f + 4, 4 * h:4 * h + 4], np.eye(3))
+            if f == h:
+                blk = blk - np.eye(12) + A    # the clover term replaces the 1
+            R[..., 12 * f:12 * f + 12, 12 * h:12 * h + 12] = blk
+    return replace(p, csw=csw, clover_R=R, clover_Rinv=np.linalg.inv(R))
 
 
 # --- full-system solves (Sec. 2.2: solution types) ---------------------------

@@ -101,3 +101,55 @@ def parity_index(dims, parity, nf):
                         i = site_index([x, y, z, t], dims)
                         idx.extend(range(i * n, (i + 1) * n))
     return np.array(idx)
+
+
+def clover_blocks(dims, U, kappa, csw, gam=None):
+    """Per-site clover term 1 + i kappa c_sw sum_{mu<nu} sigma_munu F_munu on
+    (spin, colour), [V, 12, 12] in lex order, from explicit coordinate loops:
+    F = (Q - Q^+)/8, Q the four counter-clockwise plaquette leaves at x."""
+    lx, ly, lz, lt = dims
+    V = lx * ly * lz * lt
+    g = gammas() if gam is None else gam
+    out = np.zeros((V, 12, 12), complex)
+
+    def link(mu, c):
+        c = [c[i] % dims[i] for i in range(4)]
+        return U[mu, c[3], c[2], c[1], c[0]]
+
+    def step(c, mu, d):
+        c = list(c)
+        c[mu] += d
+        return c
+
+    for t in range(lt):
+        for z in range(lz):
+            for y in range(ly):
+                for x in range(lx):
+                    c = [x, y, z, t]
+                    A = np.eye(12, dtype=complex)
+                    for mu in range(4):
+                        for nu in range(mu + 1, 4):
+                            H = lambda m: m.conj().T
+                            cm, cn = step(c, mu, -1), step(c, nu, -1)
+                            q = (link(mu, c) @ link(nu, step(c, mu, 1)) @ H(link(mu, step(c, nu, 1))) @ H(link(nu, c))
+                                 + link(nu, c) @ H(link(mu, step(cm, nu, 1))) @ H(link(nu, cm)) @ link(mu, cm)
+                                 + H(link(mu, cm)) @ H(link(nu, step(cm, nu, -1))) @ link(mu, step(cm, nu, -1)) @ link(nu, cn)
+                                 + H(link(nu, cn)) @ link(mu, cn) @ link(nu, step(cn, mu, 1)) @ H(link(mu, c)))
+                            F = (q - q.conj().T) / 8
+                            sig = 0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu])
+                            A = A + 1j * kappa * csw * np.kron(sig, F)
+                    out[site_index(c, dims)] = A
+    return out
+
+
+def dense_M_clover(dims, U, kappa, mu, csw, eps=0.0, nf=1, sign=1, tsign=-1.0):
+    """Dense twisted-clover M = A + i a g5 t3 + b t1 - kappa D."""
+    V = int(np.prod(dims))
+    M = dense_M(dims, U, kappa, mu, eps, nf, sign, tsign)
+    A = clover_blocks(dims, U, kappa, csw)
+    n = 12 * nf
+    for i in range(V):
+        for f in range(nf):
+            o = i * n + 12 * f
+            M[o:o + 12, o:o + 12] += A[i] - np.eye(12)
+    return M
