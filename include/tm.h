@@ -110,6 +110,12 @@ typedef struct {
     double epsilon;       /* bare flavour splitting of Eq. (2.1); doublet only   */
     int flavor;           /* tm_flavor                                          */
     int t_antiperiodic;   /* 1: antiperiodic in t, 0: periodic                  */
+    double csw;           /* twisted clover (Sec. 4, future work): c_sw of
+                             R(x) = A(x) + i a g5 t3 + b t1,
+                             A = 1 + i kappa c_sw sum_{mu<nu} sigma_munu F_munu,
+                             sigma_munu = (i/2)[g_mu, g_nu], F_munu = (Q - Q^+)/8
+                             with Q the four plaquette leaves at x; 0: none.
+                             FP64 / FP32 only; not with 8-real links or tm_force. */
 } tm_params;
 
 typedef struct {

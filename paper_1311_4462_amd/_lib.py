@@ -19,7 +19,8 @@ class TMError(RuntimeError):
 
 class tm_params(ctypes.Structure):
     _fields_ = [("dims", c_int * 4), ("kappa", c_double), ("mu", c_double),
-                ("epsilon", c_double), ("flavor", c_int), ("t_antiperiodic", c_int)]
+                ("epsilon", c_double), ("flavor", c_int), ("t_antiperiodic", c_int),
+                ("csw", c_double)]
 
 
 class tm_cg_params(ctypes.Structure):

@@ -33,14 +33,15 @@ def _ptr(t) -> int | None:
     return int(t)
 
 
-def make_params(dims, kappa, mu, eps=0.0, flavor=PLUS, t_antiperiodic=True) -> tm_params:
-    """dims = (Lx, Ly, Lz, Lt)."""
+def make_params(dims, kappa, mu, eps=0.0, flavor=PLUS, t_antiperiodic=True, csw=0.0) -> tm_params:
+    """dims = (Lx, Ly, Lz, Lt); csw != 0 selects the twisted-clover operator."""
     p = tm_params()
     for i in range(4):
         p.dims[i] = int(dims[i])
     p.kappa, p.mu, p.epsilon = float(kappa), float(mu), float(eps)
     p.flavor = int(flavor)
     p.t_antiperiodic = 1 if t_antiperiodic else 0
+    p.csw = float(csw)
     return p
 
 

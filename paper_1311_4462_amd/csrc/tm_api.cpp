@@ -46,6 +46,10 @@ struct tm_gauge {
     int nf = 1;
     uint32_t vh = 0;
     void *links[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    // twisted clover (csw != 0): A and B blocks per site, FP64 / FP32, per parity
+    void *clov[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool clover() const { return p.csw != 0.0; }
+    const void *clov_of(int prec, int par) const { return prec <= TM_FP32 ? clov[prec][par] : nullptr; }
 };
 
 namespace {
@@ -90,7 +94,8 @@ int check_params(tm_ctx *ctx, const tm_params *p)
     if (V / 2 > 2.0e8) return fail(ctx, TM_ERR_LIMIT, "lattice too large for one device");
     if (p->flavor != TM_TWIST_PLUS && p->flavor != TM_TWIST_MINUS && p->flavor != TM_TWIST_NDEG)
         return fail(ctx, TM_ERR_ARG, "bad twist flavor %d", p->flavor);
-    if (!std::isfinite(p->kappa) || !std::isfinite(p->mu) || !std::isfinite(p->epsilon))
+    if (!std::isfinite(p->kappa) || !std::isfinite(p->mu) || !std::isfinite(p->epsilon) ||
+        !std::isfinite(p->csw))
         return fail(ctx, TM_ERR_ARG, "non-finite operator parameter");
     const double a = 2 * p->kappa * p->mu;
     const double b = p->flavor == TM_TWIST_NDEG ? 2 * p->kappa * p->epsilon : 0.0;
@@ -167,6 +172,15 @@ double *host_scratch(tm_ctx *ctx, size_t n, int *rc)
     return ctx->host_scratch;
 }
 
+// Input-parity temporary of a twist-on-load pass (twisted clover), one per
+// problem slot and precision.
+void *twl_tmp(tm_ctx *ctx, int slot, const tm_gauge *g, int prec, int nrhs, int *rc)
+{
+    char name[64];
+    snprintf(name, sizeof(name), "twl_tmp_%d_%d", slot, prec);
+    return workspace(ctx, name, spinor_field_bytes(prec, g->vh, g->nf, nrhs), rc);
+}
+
 // Reduction slot i: a partial-sum buffer (stream ordered, so consecutive
 // launches can share one slot; a batched launch uses one per problem).
 struct RedSlot {
@@ -229,10 +243,11 @@ unsigned hop_lds_bytes(const HopCfg &c)
     const unsigned blocks = std::max(1u, (unsigned)(4 * c.wcap * 64 / c.bs));   // per compute unit
     return ((kLdsPerCU / blocks) + 511u) & ~511u;
 }
-std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon)
+std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon, bool clv)
 {
     if (twl) return {{256, true, 0}};
     std::vector<int> bss = (recon == 18) ? std::vector<int>{256}
+                           : clv ? std::vector<int>{64, 256}
                            : (nr == 1) ? std::vector<int>{64, 128, 256} : std::vector<int>{128, 256};
     std::vector<HopCfg> out;
     for (int b : bss)
@@ -251,10 +266,12 @@ HopCfg default_cfg(int twl, size_t working_set)
     return {256, working_set > (size_t)200 << 20, 0};
 }
 
-std::string tune_key(int prec, int nf, int nr, int dagger, int twl, int epi, int recon, long vh_total)
+std::string tune_key(int prec, int nf, int nr, int dagger, int twl, int epi, int recon, long vh_total,
+                     bool clv)
 {
     char key[128];
-    snprintf(key, sizeof(key), "hop_p%d_f%d_r%d_d%d_t%d_e%d_c%d_v%ld", prec, nf, nr, dagger, twl, epi, recon,
+    snprintf(key, sizeof(key), "hop_p%d_f%d_r%d_d%d_t%d_e%d_c%d%s_v%ld", prec, nf, nr, dagger, twl, epi, recon,
+             clv ? "w" : "",
              vh_total);
     return key;
 }
@@ -283,14 +300,14 @@ void load_tune(tm_ctx *ctx)
 }
 
 hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger, int twl, int recon,
-                        const HopCfg &c, hipStream_t st)
+                        const HopCfg &c, bool clv, hipStream_t st)
 {
     const unsigned lds = hop_lds_bytes(c);
     switch (prec) {
-    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
-    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
-    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
-    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, st);
+    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
+    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
+    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
+    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
     }
     return hipErrorInvalidValue;
 }
@@ -324,6 +341,8 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
         hp.k = c.k;
         hp.gauge[0] = g->links[prec][0];
         hp.gauge[1] = g->links[prec][1];
+        hp.clov = g->clov_of(prec, c.out_parity);
+        if (g->clover() && !hp.clov) return fail(ctx, TM_ERR_PREC, "clover term not built in precision %d", prec);
         hp.in = sptr(c.in, prec, g->vh, nf, c.nrhs);
         hp.out = sptr(c.out, prec, g->vh, nf, c.nrhs);
         hp.x = c.x ? sptr(c.x, prec, g->vh, nf, c.nrhs) : SpinorPtr{nullptr, nullptr};
@@ -371,11 +390,32 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     const tm_gauge *g0 = calls[0].g;
     const int prec = calls[0].prec, nf = g0->nf, recon = g0->recon;
     const int dagger = calls[0].dagger, twl = calls[0].twl;
+    const bool clv = g0->clover();
+    if (clv && twl) {
+        // twisted clover: the neighbours' R^-1 (R^-+) is a separate pass over
+        // the input into a temporary of the input parity, then a plain hop
+        HopCall pre[kMaxProblems];
+        for (int i = 0; i < n; i++) {
+            const HopCall &c = calls[i];
+            int rc = TM_OK;
+            void *tmp = twl_tmp(ctx, i, c.g, prec, c.nrhs, &rc);
+            if (!tmp) return rc;
+            const void *cl = c.g->clov_of(prec, 1 - c.out_parity);
+            if (!cl) return fail(ctx, TM_ERR_PREC, "clover term not built in precision %d", prec);
+            TM_HIP(ctx, twist_apply(prec, nf, sptr(tmp, prec, c.g->vh, nf, c.nrhs),
+                                    sptr(c.in, prec, c.g->vh, nf, c.nrhs), c.g->vh, c.nrhs,
+                                    make_twist(c.g->p, c.dagger), 1, ctx->stream, cl));
+            pre[i] = c;
+            pre[i].in = tmp;
+            pre[i].twl = 0;
+        }
+        return launch_hops(ctx, pre, n);
+    }
     int nr = 1 << 30;
     for (int i = 0; i < n; i++) nr = std::min(nr, choose_nr(prec, nf, calls[i].nrhs, recon));
     for (int i = 0; i < n; i++)
-        if (calls[i].nrhs % nr) nr = 1;
-    const std::vector<HopCfg> cand = cfg_candidates(nr, twl, recon);
+        if (calls[i].nrhs % nr || clv) nr = 1;
+    const std::vector<HopCfg> cand = cfg_candidates(nr, twl, recon, clv);
     long vh_total = 0;
     size_t wset = 0;
     for (int i = 0; i < n; i++) {
@@ -384,7 +424,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         wset += 2 * gauge_parity_bytes(prec, recon, g->vh) + 3 * spinor_field_bytes(prec, g->vh, nf, calls[i].nrhs);
     }
     HopCfg cfg = default_cfg(twl, wset);
-    const std::string key = tune_key(prec, nf, nr, dagger, twl, calls[0].epi, recon, vh_total);
+    const std::string key = tune_key(prec, nf, nr, dagger, twl, calls[0].epi, recon, vh_total, clv);
     auto it = ctx->tuned.find(key);
     if (ctx->force_bs || ctx->force_lnt >= 0) {
         HopCfg want{ctx->force_bs ? ctx->force_bs : cfg.bs, ctx->force_lnt >= 0 ? ctx->force_lnt != 0 : cfg.lnt,
@@ -406,10 +446,10 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             for (const HopCfg &c : cand) {
                 HopBatch B;
                 TM_TRY(build_hop_batch(ctx, calls, n, nr, c.bs, &B));
-                TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, ctx->stream));
+                TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
                 for (int r = 0; r < 4; r++)
-                    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, ctx->stream));
+                    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e1, ctx->stream));
                 TM_HIP(ctx, hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -428,7 +468,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     }
     HopBatch B;
     TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B));
-    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg, ctx->stream));
+    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg, clv, ctx->stream));
     TM_TRY(finish_reductions(ctx, B.p, n));
     return TM_OK;
 }
@@ -562,6 +602,8 @@ int check_gauge_prec(tm_ctx *ctx, const tm_gauge *g, int prec)
     if (!g) return fail(ctx, TM_ERR_ARG, "null gauge");
     if (!valid_prec(prec)) return fail(ctx, TM_ERR_PREC, "bad precision %d", prec);
     if (!g->links[prec][0]) return fail(ctx, TM_ERR_PREC, "gauge not built in precision %d", prec);
+    if (g->clover() && prec > TM_FP32)
+        return fail(ctx, TM_ERR_PREC, "the twisted-clover operator runs in FP64 and FP32");
     return TM_OK;
 }
 
@@ -648,6 +690,11 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const t
         return fail(ctx, TM_ERR_ARG, "t_antiperiodic must be 0 or 1");
     if (recon != 12 && recon != 18 && recon != 8) return fail(ctx, TM_ERR_ARG, "recon must be 8, 12 or 18");
     if (prec_mask == 0 || (prec_mask & ~0xFu)) return fail(ctx, TM_ERR_PREC, "bad precision mask");
+    if (p->csw != 0.0) {
+        if (prec_mask & ~((1u << TM_FP64) | (1u << TM_FP32)))
+            return fail(ctx, TM_ERR_PREC, "the twisted-clover operator runs in FP64 and FP32");
+        if (recon == 8) return fail(ctx, TM_ERR_ARG, "twisted clover with 12- or 18-real links");
+    }
     int rc = TM_OK;
     int *bad = (int *)workspace(ctx, "gauge_bad", sizeof(int), &rc);
     if (!bad) return rc;
@@ -673,6 +720,28 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const t
             return fail(ctx, TM_ERR_HIP, "gauge pack: %s", hipGetErrorString(e));
         }
     }
+    if (g->clover()) {
+        void *d[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+        for (int prec = 0; prec < 2; prec++) {
+            if (!(prec_mask & (1u << prec))) continue;
+            for (int par = 0; par < 2; par++) {
+                if (hipMalloc(&g->clov[prec][par], clover_parity_bytes(prec, g->vh)) != hipSuccess) {
+                    g->clov[prec][par] = nullptr;
+                    tm_gauge_destroy(g);
+                    return fail(ctx, TM_ERR_NOMEM, "cannot allocate the clover term");
+                }
+                d[prec][par] = g->clov[prec][par];
+            }
+        }
+        const double a = 2 * p->kappa * p->mu;
+        const double b = p->flavor == TM_TWIST_NDEG ? 2 * p->kappa * p->epsilon : 0.0;
+        hipError_t ce = clover_build(d[0][0] ? d[0] : nullptr, d[1][0] ? d[1] : nullptr, links_dev, p->dims,
+                                     g->vh, p->kappa * p->csw, a * a - b * b, bad, ctx->stream);
+        if (ce != hipSuccess) {
+            tm_gauge_destroy(g);
+            return fail(ctx, TM_ERR_HIP, "clover build: %s", hipGetErrorString(ce));
+        }
+    }
     int hbad = 0;
     hipError_t e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -682,6 +751,8 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **gout, const void *links_dev, const t
     }
     if (hbad) {
         tm_gauge_destroy(g);
+        if (p->csw != 0.0)
+            return fail(ctx, TM_ERR_SINGULAR, "twisted clover: A^2 + a^2 - b^2 is singular at some site");
         return fail(ctx, TM_ERR_ARG, "8-real links: a link has |U01|^2 + |U02|^2 < 1e-10 "
                                      "(not representable; use 12 or 18)");
     }
@@ -697,6 +768,9 @@ int tm_gauge_destroy(tm_gauge *g)
     for (int prec = 0; prec < 4; prec++)
         for (int par = 0; par < 2; par++)
             if (g->links[prec][par]) (void)hipFree(g->links[prec][par]);
+    for (int prec = 0; prec < 2; prec++)
+        for (int par = 0; par < 2; par++)
+            if (g->clov[prec][par]) (void)hipFree(g->clov[prec][par]);
     delete g;
     return TM_OK;
 }
@@ -788,7 +862,8 @@ int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec 
     if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
     TM_HIP(ctx, twist_apply(prec, g->nf, sptr(out, prec, g->vh, g->nf, nrhs),
                             sptr(in, prec, g->vh, g->nf, nrhs), g->vh, nrhs,
-                            make_twist(g->p, dagger ? 1 : 0), inverse ? 1 : 0, ctx->stream));
+                            make_twist(g->p, dagger ? 1 : 0), inverse ? 1 : 0, ctx->stream,
+                            g->clov_of(prec, parity)));
     return TM_OK;
 }
 
@@ -1057,6 +1132,10 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         int rc = TM_OK;
         if (!odd_tmp(ctx, i, pr[i].g, TM_FP64, pr[i].nrhs, &rc)) return rc;
         if (!odd_tmp(ctx, i, pr[i].g, inner, pr[i].nrhs, &rc)) return rc;
+        if (pr[i].g->clover()) {
+            if (!twl_tmp(ctx, i, pr[i].g, TM_FP64, pr[i].nrhs, &rc)) return rc;
+            if (!twl_tmp(ctx, i, pr[i].g, inner, pr[i].nrhs, &rc)) return rc;
+        }
     }
 
     const tm_gauge *gs[kMaxProblems];
@@ -1598,7 +1677,7 @@ int tm_solve(tm_ctx *ctx, void *x_e, void *x_o, const void *b_e, const void *b_o
                                 FIN_NONE, nullptr));
             TM_HIP(ctx, twist_apply(TM_FP64, g->nf, sptr(y_e, TM_FP64, g->vh, g->nf, nrhs),
                                     sptr(e1, TM_FP64, g->vh, g->nf, nrhs), g->vh, nrhs,
-                                    make_twist(g->p, 1), 1, ctx->stream));
+                                    make_twist(g->p, 1), 1, ctx->stream, g->clov_of(TM_FP64, 0)));
         }
         // y_o = R_oo^-+ (b_o + kappa D^+_oe y_e)
         TM_TRY(hop1(ctx, HopCall{g, TM_FP64, 1, 1, 0, TM_EPI_TWINV_X_PLUS_KD, y_e, y_o, b_o, kappa,
@@ -1655,6 +1734,7 @@ int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm
     if (!std::isfinite(coeff)) return fail(ctx, TM_ERR_ARG, "non-finite coeff");
     if (g->recon != 12 && g->recon != 18)
         return fail(ctx, TM_ERR_ARG, "the force kernel reads 12- or 18-real links");
+    if (g->clover()) return fail(ctx, TM_ERR_ARG, "no force for the twisted-clover operator");
     int rc = TM_OK;
     const size_t fb = spinor_field_bytes(prec, g->vh, g->nf, 1);
     void *Y = workspace(ctx, "force_y", fb, &rc);

@@ -157,7 +157,8 @@ hipError_t spinor_unpack(int prec, void *dst, SpinorPtr src, const int *X, uint3
 // ---------------------------------------------------------------- twist
 
 template <int P, int NF>
-__global__ void twist_kernel(SpinorPtr out, SpinorPtr in, uint32_t vh, Twist tw, int inverse)
+__global__ void twist_kernel(SpinorPtr out, SpinorPtr in, uint32_t vh, Twist tw, int inverse,
+                             const void *clov)
 {
     using real = typename Prec<P>::real;
     const uint32_t cb = blockIdx.x * blockDim.x + threadIdx.x;
@@ -165,17 +166,25 @@ __global__ void twist_kernel(SpinorPtr out, SpinorPtr in, uint32_t vh, Twist tw,
     if (cb >= vh) return;
     cx<real> v[NF][12];
     for (int f = 0; f < NF; f++) SpinorIO<P>::template load<0, 12>(v[f], in, vh, rhs * NF + f, cb);
-    apply_twist<real, NF>(v, tw, inverse != 0);
+    if constexpr (P == TM_FP64 || P == TM_FP32) {
+        if (clov)
+            apply_clover<P, NF>(v, clov, vh, cb, tw, inverse != 0);
+        else
+            apply_twist<real, NF>(v, tw, inverse != 0);
+    } else {
+        apply_twist<real, NF>(v, tw, inverse != 0);
+    }
     for (int f = 0; f < NF; f++) SpinorIO<P>::store(out, vh, rhs * NF + f, cb, v[f]);
 }
 
 hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t vh, int nrhs,
-                       Twist tw, int inverse, hipStream_t st)
+                       Twist tw, int inverse, hipStream_t st, const void *clov)
 {
     dim3 grid((vh + 255) / 256, nrhs);
 #define TM_TW(P, NF)                                                                            \
     if (prec == P && nf == NF) {                                                                \
-        hipLaunchKernelGGL((twist_kernel<P, NF>), grid, dim3(256), 0, st, out, in, vh, tw, inverse); \
+        hipLaunchKernelGGL((twist_kernel<P, NF>), grid, dim3(256), 0, st, out, in, vh, tw, inverse, \
+                           clov);                                                               \
         return hipGetLastError();                                                               \
     }
     TM_TW(TM_FP64, 1) TM_TW(TM_FP64, 2) TM_TW(TM_FP32, 1) TM_TW(TM_FP32, 2)

@@ -310,10 +310,14 @@ constexpr int fence_mode()
         if (fence_mode<P, NF, NR>() == 2) dir_fence(acc); \
     } while (0)
 
-template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int BS>
+// CLV: twisted clover, the epilogue's twist is the per-site R(x) (clover
+// blocks of the output parity); twist-on-load is not combined with it.
+template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int BS, bool CLV = false>
 __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const HopBatch B)
 {
     using real = typename Prec<P>::real;
+    static_assert(!CLV || (!TWL && NR == 1 && !nd_split<NF>() && (P == TM_FP64 || P == TM_FP32)),
+                  "clover epilogues: FP64 / FP32, one rhs per thread, no twist-on-load");
     __shared__ double red_sh[BS / 64];
     if (B.gate && *B.gate == 0) return;   // gated launch not needed this iteration
 
@@ -445,18 +449,26 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 cx<real> (&A)[NFT][12] = acc[r];
-                if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) apply_twist<real, NF>(A, pb.tw, true);
+                auto twist = [&](cx<real> (&v)[NF][12], bool inverse) {
+                    if constexpr (CLV) {
+                        if constexpr (P == TM_FP64 || P == TM_FP32)
+                            apply_clover<P, NF>(v, pb.clov, vh, cb, pb.tw, inverse);
+                    } else {
+                        apply_twist<real, NF>(v, pb.tw, inverse);
+                    }
+                };
+                if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) twist(A, true);
                 if (epi >= TM_EPI_RX_PLUS_KD) {
                     cx<real> X[NF][12];
 #pragma unroll
                     for (int f = 0; f < NF; f++)
                         SpinorIO<P>::template load<0, 12>(X[f], pb.x, vh, (uint32_t)((r0 + r) * NF + f), cb);
-                    if (epi == TM_EPI_RX_PLUS_KD) apply_twist<real, NF>(X, pb.tw, false);
+                    if (epi == TM_EPI_RX_PLUS_KD) twist(X, false);
 #pragma unroll
                     for (int f = 0; f < NF; f++)
 #pragma unroll
                         for (int k = 0; k < 12; k++) A[f][k] = X[f][k] + kk * A[f][k];
-                    if (epi == TM_EPI_TWINV_X_PLUS_KD) apply_twist<real, NF>(A, pb.tw, true);
+                    if (epi == TM_EPI_TWINV_X_PLUS_KD) twist(A, true);
                 }
 #pragma unroll
                 for (int f = 0; f < NF; f++) {
@@ -485,12 +497,26 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
 // Host-side dispatch over the compile-time variants built for precision P.
 
 #define TM_HOP_CASE(P, NF, NR, DAG, TWL, RECON, LNT, BS)                                          \
-    if (nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON && lnt == LNT &&      \
-        bs == BS) {                                                                                 \
+    if (!clv && nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON &&           \
+        lnt == LNT && bs == BS) {                                                                   \
         hipLaunchKernelGGL((hop_kernel<P, NF, NR, DAG, TWL, RECON, LNT, BS>), dim3(B.total_blocks), \
                            dim3(BS), lds, st, B);                                                   \
         return hipGetLastError();                                                                   \
     }
+
+// twisted-clover epilogues (FP64 / FP32, one rhs per thread, no twist-on-load)
+#define TM_HOP_CASE_CLV(P, NF, DAG, RECON, LNT, BS)                                                 \
+    if (clv && nf == NF && nr == 1 && dagger == DAG && twl == 0 && recon == RECON && lnt == LNT &&  \
+        bs == BS) {                                                                                 \
+        hipLaunchKernelGGL((hop_kernel<P, NF, 1, DAG, false, RECON, LNT, BS, true>),                \
+                           dim3(B.total_blocks), dim3(BS), lds, st, B);                             \
+        return hipGetLastError();                                                                   \
+    }
+#define TM_HOP_CASES_CLV(P, NF, RECON, BS)               \
+    TM_HOP_CASE_CLV(P, NF, 0, RECON, true, BS)           \
+    TM_HOP_CASE_CLV(P, NF, 1, RECON, true, BS)           \
+    TM_HOP_CASE_CLV(P, NF, 0, RECON, false, BS)          \
+    TM_HOP_CASE_CLV(P, NF, 1, RECON, false, BS)
 
 // both daggers, both link-load policies
 #define TM_HOP_CASES(P, NF, NR, RECON, BS)          \
@@ -507,8 +533,17 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const
 #define TM_HOP_DEFINE(P)                                                                       \
     template <>                                                                                \
     hipError_t launch_hop_prec<P>(const HopBatch &B, int nf, int nr, int dagger, int twl,      \
-                                  int recon, int bs, bool lnt, unsigned lds, hipStream_t st)   \
+                                  int recon, int bs, bool lnt, unsigned lds, bool clv,         \
+                                  hipStream_t st)                                              \
     {                                                                                          \
+        if constexpr (P == TM_FP64 || P == TM_FP32) {                                          \
+            TM_HOP_CASES_CLV(P, 1, 12, 256)                                                    \
+            TM_HOP_CASES_CLV(P, 1, 12, 64)                                                     \
+            TM_HOP_CASES_CLV(P, 2, 12, 256)                                                    \
+            TM_HOP_CASES_CLV(P, 2, 12, 64)                                                     \
+            TM_HOP_CASES_CLV(P, 1, 18, 256)                                                    \
+            TM_HOP_CASES_CLV(P, 2, 18, 256)                                                    \
+        }                                                                                      \
         TM_HOP_CASES(P, 1, 1, 12, 256)                                                         \
         TM_HOP_CASES(P, 1, 1, 12, 128)                                                         \
         TM_HOP_CASES(P, 1, 1, 12, 64)                                                          \

@@ -542,6 +542,148 @@ __device__ __forceinline__ void apply_twist(cx<T> (&v)[NF][12], const Twist &tw,
         for (int k = 0; k < 12; k++) v[f][k] = o[f][k];
 }
 
+// ------------------------------------------------------------------ clover
+//
+// Twisted clover (the future work of Sec. 4): R(x) = A(x) + i a g5 t3 + b t1.
+// A commutes with g5, so in the chiral basis (g5 = diag(1, 1, -1, -1)) it is
+// two Hermitian 6x6 blocks A_+, A_- on (spin pair, colour).  Per block the
+// doublet twist is [[A + i a chi, b], [b, A - i a chi]] in flavour space, whose
+// inverse is B [[A - i a chi, -b], [-b, A + i a chi]] with the Hermitian
+// B = (A^2 + a^2 - b^2)^-1 (A commutes with the scalars).  Stored per site:
+// A_+, A_-, B_+, B_-, each as 36 reals (6 real diagonal entries, then the 15
+// upper off-diagonal entries (i < j, row-major) as re, im), in 16-byte chunk
+// rows [block][chunk][cb] (FP64: 18 chunks per block, FP32: 9).
+// The internal basis maps to the chiral one by psi_+ = (psi_0,1 + psi_2,3),
+// psi_- = (psi_0,1 - psi_2,3) (times 1/sqrt 2, applied as 1/2 on the way back).
+
+__host__ __device__ inline size_t clover_parity_bytes(int prec, long vh)
+{
+    return (size_t)4 * 36 * (prec == TM_FP64 ? 8 : 4) * vh;
+}
+
+template <int P>
+struct CloverIO {
+    using real = typename Prec<P>::real;
+    static constexpr int NCH = (P == TM_FP64) ? 18 : 9;   // 16-byte chunks per block
+
+    __device__ static __forceinline__ void load(real (&d)[36], const void *base, uint32_t vh, int blk,
+                                                uint32_t cb)
+    {
+        const uint32_t o16 = cb * 16u;
+        if constexpr (P == TM_FP64) {
+#pragma unroll
+            for (int k = 0; k < NCH; k++) {
+                const double2 c = *at<double2>((const char *)base + ((size_t)blk * NCH + k) * vh * 16, o16);
+                d[2 * k] = c.x;
+                d[2 * k + 1] = c.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NCH; k++) {
+                const float4 c = *at<float4>((const char *)base + ((size_t)blk * NCH + k) * vh * 16, o16);
+                d[4 * k] = c.x;
+                d[4 * k + 1] = c.y;
+                d[4 * k + 2] = c.z;
+                d[4 * k + 3] = c.w;
+            }
+        }
+    }
+
+    __device__ static __forceinline__ void store(void *base, uint32_t vh, int blk, uint32_t cb,
+                                                 const double (&d)[36])
+    {
+        const uint32_t o16 = cb * 16u;
+        for (int k = 0; k < NCH; k++) {
+            char *row = (char *)base + ((size_t)blk * NCH + k) * vh * 16;
+            if constexpr (P == TM_FP64)
+                *at_w<double2>(row, o16) = make_double2(d[2 * k], d[2 * k + 1]);
+            else
+                *at_w<float4>(row, o16) = make_float4((float)d[4 * k], (float)d[4 * k + 1],
+                                                      (float)d[4 * k + 2], (float)d[4 * k + 3]);
+        }
+    }
+};
+
+// w = H v for a packed Hermitian 6x6 H
+template <typename T>
+__device__ __forceinline__ void herm6_mv(cx<T> (&w)[6], const T (&h)[36], const cx<T> (&v)[6])
+{
+#pragma unroll
+    for (int i = 0; i < 6; i++) w[i] = h[i] * v[i];
+    int o = 6;
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+#pragma unroll
+        for (int j = i + 1; j < 6; j++) {
+            const cx<T> e = mk(h[o], h[o + 1]);
+            o += 2;
+            w[i] = w[i] + cmul(e, v[j]);
+            w[j] = w[j] + cjmul(e, v[i]);
+        }
+}
+
+// w_chi <- R w_chi or R^-1 w_chi on one chiral block (all flavours)
+template <int P, int NF>
+__device__ __forceinline__ void clover_block(cx<typename Prec<P>::real> (&w)[NF][6], const void *clov,
+                                             uint32_t vh, uint32_t cb, int chi, const Twist &tw,
+                                             bool inverse)
+{
+    using T = typename Prec<P>::real;
+    const T s = inverse ? (T)-1 : (T)1;
+    const T sg = chi == 0 ? (T)1 : (T)-1;                // g5 on this block
+    const T b = (T)tw.b;
+    T h[36];
+    CloverIO<P>::load(h, clov, vh, chi, cb);
+    cx<T> u[NF][6];
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+        herm6_mv(u[f], h, w[f]);
+        const T t3 = (f == 0 ? (T)tw.ta : (T)-tw.ta) * sg * s;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            u[f][k] = u[f][k] + t3 * times_i(w[f][k]);
+            if constexpr (NF == 2) u[f][k] = u[f][k] + (s * b) * w[1 - f][k];
+        }
+    }
+    if (inverse) {
+        CloverIO<P>::load(h, clov, vh, 2 + chi, cb);
+#pragma unroll
+        for (int f = 0; f < NF; f++) herm6_mv(w[f], h, u[f]);
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; f++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) w[f][k] = u[f][k];
+    }
+}
+
+// v <- R v or R^-1 v (R^+ / R^-+ through the sign of tw.ta) with the clover
+// term of this site.
+template <int P, int NF>
+__device__ __forceinline__ void apply_clover(cx<typename Prec<P>::real> (&v)[NF][12], const void *clov,
+                                             uint32_t vh, uint32_t cb, const Twist &tw, bool inverse)
+{
+    using T = typename Prec<P>::real;
+    cx<T> wp[NF][6], wm[NF][6];
+#pragma unroll
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            wp[f][k] = v[f][k] + v[f][k + 6];
+            wm[f][k] = v[f][k] - v[f][k + 6];
+        }
+    clover_block<P, NF>(wp, clov, vh, cb, 0, tw, inverse);
+    clover_block<P, NF>(wm, clov, vh, cb, 1, tw, inverse);
+    // back to the internal basis, the two 1/sqrt 2 factors as one 1/2
+#pragma unroll
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            v[f][k] = (T)0.5 * (wp[f][k] + wm[f][k]);
+            v[f][k + 6] = (T)0.5 * (wp[f][k] - wm[f][k]);
+        }
+}
+
 // ------------------------------------------------------------------ reductions
 
 // CG scalars per right-hand side, device resident.
@@ -682,6 +824,7 @@ struct HopProblem {
     Twist tw;            // twist (dagger sign folded in)
     double k;            // epilogue coefficient
     const void *gauge[2];   // links of parity 0 / 1
+    const void *clov;       // clover blocks of the output parity (twisted clover)
     SpinorPtr in, out, x;
     Reduce red;
 };

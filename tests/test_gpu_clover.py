@@ -1,0 +1,148 @@
+"""Twisted clover (R(x) = A(x) + i a g5 t3 + b t1 with the four-leaf clover term)
+through the C ABI against the FP64 oracle: operator applies in FP64 and FP32,
+every fused epilogue, the standalone twist, prepare / reconstruct, CG (plain,
+mixed, graph-captured) and the full-system solve.  Tolerances as for twisted
+mass: 1e-12 FP64, 1e-5 FP32 (norm-wise relative), solves to 1e-10."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1311_4462_amd import inputs
+from tests.gpu_util import TOL, from_native, oparams, oracle_dslash, rel, to_native
+
+pytestmark = pytest.mark.gpu
+
+CSW = 1.57
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_4462_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context()
+    yield c
+    c.close()
+
+
+def _setup(api, ctx, dims, flavor, seed=71, kind="haar", recon=12, precs=(0, 1), kappa=0.16):
+    p = api.make_params(dims, kappa, 0.13, 0.17 if flavor == api.NDEG else 0.0, flavor, csw=CSW)
+    U = inputs.gauge_field(dims, kind, seed)
+    g = api.Gauge(ctx, U, p, recon=recon, precs=precs)
+    op = O.with_clover(oparams(p), U, CSW)
+    return p, op, U, g
+
+
+@pytest.mark.parametrize("flavor", [1, -1, 2])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_clover_mat_pc(api, ctx, flavor, prec):
+    dims = (8, 6, 4, 10)
+    p, op, U, g = _setup(api, ctx, dims, flavor)
+    x = O.project(inputs.gaussian_spinor(dims, op.nf, 72), dims, 0)
+    t = to_native(api, ctx, x, p, prec, 0)
+    out = api.new_field(p, prec)
+    for pc in (0, 1):
+        for dag in (0, 1):
+            api.tm_mat_pc(ctx, out, t, g, prec, pc, dag)
+            ref = O.mat_pc(op, U, x, "asym" if pc == 0 else "sym", bool(dag))
+            assert rel(from_native(api, ctx, out, p, prec, 0)[0], ref) < TOL[prec], (pc, dag)
+    g.close()
+
+
+@pytest.mark.parametrize("flavor", [1, 2])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_clover_dslash_epilogues_and_twist(api, ctx, flavor, prec):
+    dims = (6, 4, 4, 6)
+    p, op, U, g = _setup(api, ctx, dims, flavor, seed=73)
+    nf = op.nf
+    for outp in (0, 1):
+        inp = O.project(inputs.gaussian_spinor(dims, nf, 74), dims, 1 - outp)
+        xv = O.project(inputs.gaussian_spinor(dims, nf, 75), dims, outp)
+        ti, tx = to_native(api, ctx, inp, p, prec, 1 - outp), to_native(api, ctx, xv, p, prec, outp)
+        out = api.new_field(p, prec)
+        for epi in range(6):
+            for dag in (0, 1):
+                for twl in (0, 1):
+                    api.tm_dslash(ctx, out, ti, g, prec, outp, dag, twl, epi, tx, -0.37)
+                    ref = oracle_dslash(op, U, inp, outp, dag, twl, epi, xv, -0.37)
+                    assert rel(from_native(api, ctx, out, p, prec, outp)[0], ref) < TOL[prec], (epi, dag, twl)
+        for dag in (0, 1):
+            for inv in (0, 1):
+                api.tm_twist(ctx, out, tx, g, prec, outp, dag, inv)
+                ref = O.twist(op, xv, inverse=bool(inv), dagger=bool(dag), parity=outp)
+                assert rel(from_native(api, ctx, out, p, prec, outp)[0], ref) < TOL[prec]
+    g.close()
+
+
+@pytest.mark.parametrize("pc", [0, 1])
+def test_clover_prepare_reconstruct_and_cg(api, ctx, pc):
+    dims = (8, 8, 8, 8)
+    p, op, U, g = _setup(api, ctx, dims, 2, seed=76, kind="near_unit", kappa=0.1615)
+    b = inputs.gaussian_spinor(dims, 2, 77)
+    pcs = "asym" if pc == 0 else "sym"
+    be, bo = to_native(api, ctx, b, p, 0, 0), to_native(api, ctx, b, p, 0, 1)
+    bh = api.new_field(p, 0)
+    api.tm_prepare(ctx, bh, be, bo, g, 0, pc)
+    bh_ref = O.prepare(op, U, b, pcs)
+    assert rel(from_native(api, ctx, bh, p, 0, 0)[0], bh_ref) < 1e-12
+    for inner in (0, 1):
+        x = api.new_field(p, 0)
+        r = api.tm_cg(ctx, x, bh, g, pc=pc, tol=1e-10, inner=inner)[0]
+        assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
+        xe = from_native(api, ctx, x, p, 0, 0)[0]
+        c = O.mat_pc(op, U, bh_ref, pcs, dagger=True)
+        assert rel(O.normal_op(op, U, xe, pcs), c) <= 1.5e-10
+    xo = api.new_field(p, 0)
+    api.tm_reconstruct_odd(ctx, xo, x, bo, g, 0)
+    psi = xe + from_native(api, ctx, xo, p, 0, 1)[0]
+    assert rel(O.full_M(op, U, psi), b) < 1e-8
+    g.close()
+
+
+def test_clover_graph_cg_and_full_solve(api, ctx):
+    dims = (8, 8, 8, 8)
+    p, op, U, g = _setup(api, ctx, dims, 1, seed=78, kind="near_unit", kappa=0.1615)
+    b = inputs.gaussian_spinor(dims, 1, 79)
+    be, bo = to_native(api, ctx, b, p, 0, 0), to_native(api, ctx, b, p, 0, 1)
+    # graph-captured mixed CG on the symmetric operator (its dagger twists on load)
+    x = api.new_field(p, 0)
+    r = api.tm_cg(ctx, x, be, g, pc=1, tol=1e-10, inner=1, graph_iters=8)[0]
+    assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
+    c = O.mat_pc(op, U, O.project(b, dims, 0), "sym", dagger=True)
+    assert rel(O.normal_op(op, U, from_native(api, ctx, x, p, 0, 0)[0], "sym"), c) <= 1.5e-10
+    for solution in (0, 1):
+        xe, xo = api.new_field(p, 0), api.new_field(p, 0)
+        rr = api.tm_solve(ctx, xe, xo, be, bo, g, solution=solution, pc=1, tol=1e-11)[0]
+        assert rr["status"] == 0
+        xf = from_native(api, ctx, xe, p, 0, 0)[0] + from_native(api, ctx, xo, p, 0, 1)[0]
+        Mx = O.full_M(op, U, xf)
+        res = rel(Mx, b) if solution == 0 else rel(O.full_M(op, U, Mx, dagger=True), b)
+        assert res < 1e-8 and abs(rr["true_rel_res_full"] - res) <= 1e-3 * res + 1e-15
+    g.close()
+
+
+def test_clover_errors(api, ctx):
+    from paper_1311_4462_amd._lib import TMError
+    dims = (4, 4, 4, 4)
+    p = api.make_params(dims, 0.16, 0.1, csw=1.0)
+    U = inputs.gauge_field(dims, "haar", 80)
+    with pytest.raises(TMError) as e:
+        api.Gauge(ctx, U, p, precs=(0, 2))
+    assert e.value.code == -4
+    with pytest.raises(TMError) as e:
+        api.Gauge(ctx, U, p, recon=8, precs=(0,))
+    assert e.value.code == -1
+    g = api.Gauge(ctx, U, p, precs=(1,))
+    x = api.new_field(p, 1)
+    import torch
+    F = torch.empty((4,) + dims[::-1] + (3, 3), dtype=torch.complex64, device="cuda")
+    with pytest.raises(TMError) as e:
+        api.tm_force(ctx, F, 1, x, g, 1)
+    assert e.value.code == -1
+    g.close()
