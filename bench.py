@@ -112,7 +112,8 @@ def mat_pc_rates(torch, api, ctx, g, p, precs, reps, flops_site, recon=12):
 
 def operator_variants(torch, api, ctx, U, p, reps):
     """us per apply of the preconditioned operator, asym / sym, with and without
-    dagger, FP64 and FP32, for 18-, 12- and 8-real links."""
+    dagger, FP64 and FP32, for 18-, 12- and 8-real links; and the asymmetric
+    twisted-clover apply."""
     Ut = torch.from_numpy(U).cuda()
     src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
     out = {}
@@ -129,6 +130,23 @@ def operator_variants(torch, api, ctx, U, p, reps):
             out[f"{api.PREC_NAMES[prec]}_r{recon}"] = row
             del x, y
         g.close()
+    # twisted clover (c_sw = 1.57): the same asymmetric apply, with the clover
+    # blocks read by both kernels (A and B by the R^-1 kernel, A by the R kernel)
+    import numpy as np
+    vh = int(np.prod(tuple(p.dims))) // 2
+    pc = api.make_params(tuple(p.dims), p.kappa, p.mu, 0.0, p.flavor, csw=1.57)
+    g = api.Gauge(ctx, Ut, pc, recon=12, precs=(api.FP64, api.FP32))
+    for prec in (api.FP64, api.FP32):
+        x = api.tm_spinor_pack(ctx, src, pc, prec, 0)
+        y = api.new_field(pc, prec)
+        t = time_launches(torch, lambda: api.tm_mat_pc(ctx, y, x, g, prec, api.ASYM, 0), reps)
+        rb = 8 if prec == api.FP64 else 4
+        byt = (16 * 12 * rb + 5 * 24 * rb + 6 * 36 * rb) * vh
+        out[f"clover_{api.PREC_NAMES[prec]}_r12"] = {
+            "asym_us": round(t * 1e6, 2), "gbs": round(byt / t / 1e9, 1),
+            "bytes_per_site": byt // vh}
+        del x, y
+    g.close()
     del Ut, src
     log(f"operator variants (us): {out}")
     return out
