@@ -192,10 +192,13 @@ def cg_comparison(torch, api, inputs, reps=3):
         for _ in range(reps):
             x = api.new_field(p, api.FP64)
             torch.cuda.synchronize()
+            w0 = time.monotonic_ns()
             t0 = time.perf_counter()
             res = api.tm_cg(ctx, x, tb, g, pc=api.ASYM, tol=1e-10, maxiter=20000, inner=inner)[0]
             torch.cuda.synchronize()
             secs.append(time.perf_counter() - t0)
+            # CLOCK_MONOTONIC window of the solve, for attributing a kernel trace
+            log(f"cg window {name} {w0} {time.monotonic_ns()}")
         out[name] = {"seconds": round(statistics.median(secs), 4), "iters": res["iters"],
                      "reliable_updates": res["reliable_updates"],
                      "true_rel_res_normal": res["true_rel_res_normal"],

@@ -265,10 +265,12 @@ __device__ __forceinline__ void hop_direction(
 #ifndef TM_HOP_WAVES_ND
 #define TM_HOP_WAVES_ND 2
 #endif
-template <int P, int NF, int NR>
+template <int P, int NF, int NR, bool CLV = false>
 constexpr int hop_waves()
 {
     constexpr int NFT = flavours_per_thread<NF>();
+    // FP64 clover epilogues (two 6x6 blocks per chirality) get a wave less
+    if constexpr (CLV && P == TM_FP64) return NFT == 2 ? 1 : 2;
     return (P == TM_FP64 && NFT * NR == 1) ? 3
            : (P != TM_FP64 && NFT == 2 && NR == 1) ? TM_HOP_WAVES_ND
            : (P == TM_FP64 || NFT * NR > 1) ? 2 : TM_HOP_WAVES_LIGHT;
@@ -313,7 +315,7 @@ constexpr int fence_mode()
 // CLV: twisted clover, the epilogue's twist is the per-site R(x) (clover
 // blocks of the output parity); twist-on-load is not combined with it.
 template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int BS, bool CLV = false>
-__global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR>())) hop_kernel(const HopBatch B)
+__global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(const HopBatch B)
 {
     using real = typename Prec<P>::real;
     static_assert(!CLV || (!TWL && NR == 1 && !nd_split<NF>() && (P == TM_FP64 || P == TM_FP32)),
