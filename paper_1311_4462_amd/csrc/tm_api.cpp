@@ -1115,7 +1115,11 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     // reliable-update threshold: by default 0.01 for half-precision inner
     // iterations and 0.001 for FP32 (the residual is replaced once it has
     // dropped by 1/delta since the last replacement)
-    const double delta = par->delta > 0 ? par->delta : (inner == TM_FP32 ? 1e-3 : 1e-2);
+    // Below a floor set by the inner format's precision the iterated residual
+    // stagnates before it has dropped by delta and no update would come
+    // (measured: BF16 at 0.002 never converges), so delta is raised to it.
+    const double delta_floor = inner == TM_FP32 ? 1e-5 : (inner == TM_FP16 ? 2e-3 : 1e-2);
+    const double delta = std::max(par->delta > 0 ? par->delta : (inner == TM_FP32 ? 1e-3 : 1e-2), delta_floor);
     const int check_every = std::max(1, par->check_every);
     const int nf = pr[0].g->nf;
 

@@ -100,3 +100,19 @@ def test_error_paths(api, ctx):
         r = api.tm_cg(ctx, a, b2, g, maxiter=2)[0]
     assert r["status"] == 1 and r["iters"] == 2 and 0 < r["true_rel_res_normal"] < 1
     g.close()
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+def test_tiny_delta_is_raised_and_converges(api, ctx, inner):
+    """A reliable-update threshold below what the inner format can reach is
+    raised to its floor, so the solve still reaches the FP64 tolerance."""
+    dims = (8, 8, 8, 8)
+    p = api.make_params(dims, 0.1615, 0.15, 0.19, api.NDEG)
+    U = inputs.gauge_field(dims, "near_unit", 91)
+    g = api.Gauge(ctx, U, p, precs=(0, inner))
+    b = O.project(inputs.gaussian_spinor(dims, 2, 92), dims, 0)
+    tb = to_native(api, ctx, b, p, 0, 0)
+    x = api.new_field(p, 0)
+    r = api.tm_cg(ctx, x, tb, g, tol=1e-10, inner=inner, delta=1e-6, maxiter=2000)[0]
+    assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10 and r["reliable_updates"] >= 1
+    g.close()
