@@ -112,24 +112,30 @@ def mat_pc_rates(torch, api, ctx, g, p, precs, reps, flops_site, recon=12):
 
 def operator_variants(torch, api, ctx, U, p, reps):
     """us per apply of the preconditioned operator, asym / sym, with and without
-    dagger, FP64 and FP32, for 18-, 12- and 8-real links; and the asymmetric
+    dagger, FP64 and FP32: one flavour with 18-, 12- and 8-real links, the other
+    twist sign and the doublet with 12-real links; and the asymmetric
     twisted-clover apply."""
     Ut = torch.from_numpy(U).cuda()
-    src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
     out = {}
-    for recon in (18, 12, 8):
-        g = api.Gauge(ctx, Ut, p, recon=recon, precs=(api.FP64, api.FP32))
+    # one flavour twisted up (PLUS) with 18/12/8-real links, then twisted down
+    # (MINUS) and the doublet (eps = 0.19) with 12-real links
+    cases = [(api.PLUS, r, "") for r in (18, 12, 8)] + [(api.MINUS, 12, "_minus"), (api.NDEG, 12, "_nd")]
+    for flavor, recon, tag in cases:
+        pf = api.make_params(tuple(p.dims), p.kappa, p.mu, 0.19 if flavor == api.NDEG else 0.0, flavor)
+        src = torch.randn(api.canonical_shape(pf), dtype=torch.complex128, device="cuda")
+        g = api.Gauge(ctx, Ut, pf, recon=recon, precs=(api.FP64, api.FP32))
         for prec in (api.FP64, api.FP32):
-            x = api.tm_spinor_pack(ctx, src, p, prec, 0)
-            y = api.new_field(p, prec)
+            x = api.tm_spinor_pack(ctx, src, pf, prec, 0)
+            y = api.new_field(pf, prec)
             row = {}
             for pc, pcn in ((api.ASYM, "asym"), (api.SYM, "sym")):
                 for dag in (0, 1):
                     t = time_launches(torch, lambda: api.tm_mat_pc(ctx, y, x, g, prec, pc, dag), reps)
                     row[pcn + ("_dag" if dag else "")] = round(t * 1e6, 2)
-            out[f"{api.PREC_NAMES[prec]}_r{recon}"] = row
+            out[f"{api.PREC_NAMES[prec]}_r{recon}{tag}"] = row
             del x, y
         g.close()
+    src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
     # twisted clover (c_sw = 1.57): the same asymmetric apply, with the clover
     # blocks read by both kernels (A and B by the R^-1 kernel, A by the R kernel)
     import numpy as np
