@@ -36,6 +36,7 @@ struct tm_ctx {
     std::map<std::string, int> tuned;  // kernel key -> block size
     int force_bs = 0;                  // TM_HOP_BS: fixed block size (0: tuned / default)
     int force_lnt = -1;                // TM_LINK_NT: 1 / 0 fixes the link load policy
+    int force_zc = -1;                 // TM_HOP_ZC: fixed brick depth of the site order (0: lexicographic)
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
 };
@@ -235,7 +236,15 @@ struct HopCfg {
     int bs;
     bool lnt;
     int wcap;
+    int zc = 0;     // z-planes per brick of the site order (0: lexicographic)
 };
+// bricks of at most `target` z-planes: the largest divisor of Lz below Lz
+int zc_for(int target, int Lz)
+{
+    for (int d = std::min(target, Lz - 1); d >= 2; d--)
+        if (Lz % d == 0) return d;
+    return 0;
+}
 constexpr unsigned kLdsPerCU = 160u << 10;
 unsigned hop_lds_bytes(const HopCfg &c)
 {
@@ -314,7 +323,7 @@ hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger,
 
 // One launch of the fused hop over up to kMaxProblems problems (same
 // precision, flavour count, recon, dagger, epilogue and rhs grouping).
-int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, HopBatch *B)
+int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, HopBatch *B, int zc = 0)
 {
     const int prec = calls[0].prec, nf = calls[0].g->nf;
     memset(B, 0, sizeof(*B));
@@ -336,6 +345,7 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
         hp.nsb = (int)((g->vh + spb - 1) / spb);
         hp.ngrp = c.nrhs / nr;
         hp.out_parity = c.out_parity;
+        hp.zc = zc ? zc_for(zc, g->p.dims[2]) : 0;
         hp.tsign = g->p.t_antiperiodic ? -1.0 : 1.0;
         hp.tw = make_twist(g->p, c.dagger);
         hp.k = c.k;
@@ -432,20 +442,23 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         for (const HopCfg &c : cand)
             if (c.bs == want.bs && c.lnt == want.lnt && c.wcap == 0) cfg = want;
     } else if (it != ctx->tuned.end()) {
-        cfg = HopCfg{it->second & 0xffff, ((it->second >> 16) & 1) != 0, it->second >> 20};
+        const int code = it->second;
+        cfg = HopCfg{code & 0xffff, ((code >> 16) & 1) != 0, (code >> 20) & 0xf, (code >> 24) & 0x7f};
     } else if (ctx->tuning && cand.size() > 1) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(ctx->stream, &cs);
         if (cs == hipStreamCaptureStatusNone) {
-            // time every instantiated configuration on the real launch (hop
-            // launches are idempotent: out never aliases an input)
+            // time the instantiated configurations on the real launch (hop
+            // launches are idempotent: out never aliases an input): block size
+            // x link-load policy x wave cap in lexicographic site order, then
+            // the site order's brick depth for the best of those
             hipEvent_t e0, e1;
             TM_HIP(ctx, hipEventCreate(&e0));
             TM_HIP(ctx, hipEventCreate(&e1));
             float best = 1e30f;
-            for (const HopCfg &c : cand) {
+            auto trial = [&](const HopCfg &c) -> int {
                 HopBatch B;
-                TM_TRY(build_hop_batch(ctx, calls, n, nr, c.bs, &B));
+                TM_TRY(build_hop_batch(ctx, calls, n, nr, c.bs, &B, c.zc));
                 TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
                 for (int r = 0; r < 4; r++)
@@ -458,16 +471,25 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
                     best = ms;
                     cfg = c;
                 }
+                return TM_OK;
+            };
+            for (const HopCfg &c : cand) TM_TRY(trial(c));
+            const HopCfg base = cfg;
+            for (int z : {8, 4, 2}) {
+                HopCfg c = base;
+                c.zc = z;
+                TM_TRY(trial(c));
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0) | (cfg.wcap << 20);
+            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0) | (cfg.wcap << 20) | (cfg.zc << 24);
             ctx->tuned[key] = code;
             save_tune(ctx, key, code);
         }
     }
+    if (ctx->force_zc >= 0) cfg.zc = ctx->force_zc;
     HopBatch B;
-    TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B));
+    TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B, cfg.zc));
     TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg, clv, ctx->stream));
     TM_TRY(finish_reductions(ctx, B.p, n));
     return TM_OK;
@@ -647,6 +669,8 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (e) c->force_bs = atoi(e);
     e = getenv("TM_LINK_NT");
     if (e) c->force_lnt = atoi(e) ? 1 : 0;
+    e = getenv("TM_HOP_ZC");
+    if (e) c->force_zc = std::max(0, atoi(e));
     e = getenv("TM_TUNE");
     if (e) c->tuning = atoi(e) ? 1 : 0;
     load_tune(c);

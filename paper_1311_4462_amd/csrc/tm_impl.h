@@ -820,6 +820,7 @@ struct HopProblem {
     int nsb;             // site blocks
     int ngrp;            // rhs groups
     int out_parity;
+    int zc;              // z-planes per brick of the processing order (0: lexicographic)
     double tsign;        // factor on hops across the t boundary
     Twist tw;            // twist (dagger sign folded in)
     double k;            // epilogue coefficient

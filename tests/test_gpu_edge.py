@@ -116,3 +116,31 @@ def test_tiny_delta_is_raised_and_converges(api, ctx, inner):
     r = api.tm_cg(ctx, x, tb, g, tol=1e-10, inner=inner, delta=1e-6, maxiter=2000)[0]
     assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10 and r["reliable_updates"] >= 1
     g.close()
+
+
+@pytest.mark.parametrize("zc", [2, 3])
+def test_brick_site_order(api, zc, monkeypatch):
+    """Sites visited in bricks of zc z-planes (all time slices of a brick
+    column before the next): the same operator and the same solve."""
+    monkeypatch.setenv("TM_HOP_ZC", str(zc))
+    c = api.Context()
+    dims = (6, 4, 12, 6)
+    for flavor in (1, 2):
+        p = api.make_params(dims, 0.16, 0.13, 0.17 if flavor == 2 else 0.0, flavor)
+        op = oparams(p)
+        U = inputs.gauge_field(dims, "haar", 95)
+        g = api.Gauge(c, U, p, precs=(0, 1))
+        x = O.project(inputs.gaussian_spinor(dims, op.nf, 96), dims, 0)
+        for prec in (0, 1):
+            t = to_native(api, c, x, p, prec, 0)
+            out = api.new_field(p, prec)
+            for pc in (0, 1):
+                for dag in (0, 1):
+                    api.tm_mat_pc(c, out, t, g, prec, pc, dag)
+                    ref = O.mat_pc(op, U, x, "asym" if pc == 0 else "sym", bool(dag))
+                    assert rel(from_native(api, c, out, p, prec, 0)[0], ref) < TOL[prec]
+        tx = api.new_field(p, 0)
+        r = api.tm_cg(c, tx, to_native(api, c, x, p, 0, 0), g, tol=1e-10, inner=1)[0]
+        assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
+        g.close()
+    c.close()
