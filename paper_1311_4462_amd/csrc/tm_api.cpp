@@ -37,6 +37,7 @@ struct tm_ctx {
     int force_bs = 0;                  // TM_HOP_BS: fixed block size (0: tuned / default)
     int force_lnt = -1;                // TM_LINK_NT: 1 / 0 fixes the link load policy
     int force_zc = -1;                 // TM_HOP_ZC: fixed brick depth of the site order (0: lexicographic)
+    int force_wcap = -1;               // TM_HOP_WCAP: fixed cap of resident waves per SIMD (0: none)
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
 };
@@ -346,6 +347,13 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
         hp.ngrp = c.nrhs / nr;
         hp.out_parity = c.out_parity;
         hp.zc = zc ? zc_for(zc, g->p.dims[2]) : 0;
+        // slabs of about an eighth of the time extent (one XCD's share)
+        hp.ts = 1;
+        for (int d = (g->p.dims[3] + 7) / 8; d >= 1; d--)
+            if (g->p.dims[3] % d == 0) {
+                hp.ts = d;
+                break;
+            }
         hp.tsign = g->p.t_antiperiodic ? -1.0 : 1.0;
         hp.tw = make_twist(g->p, c.dagger);
         hp.k = c.k;
@@ -488,6 +496,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         }
     }
     if (ctx->force_zc >= 0) cfg.zc = ctx->force_zc;
+    if (ctx->force_wcap >= 0) cfg.wcap = ctx->force_wcap;
     HopBatch B;
     TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B, cfg.zc));
     TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg, clv, ctx->stream));
@@ -671,6 +680,8 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (e) c->force_lnt = atoi(e) ? 1 : 0;
     e = getenv("TM_HOP_ZC");
     if (e) c->force_zc = std::max(0, atoi(e));
+    e = getenv("TM_HOP_WCAP");
+    if (e) c->force_wcap = std::min(8, std::max(0, atoi(e)));
     e = getenv("TM_TUNE");
     if (e) c->tuning = atoi(e) ? 1 : 0;
     load_tune(c);

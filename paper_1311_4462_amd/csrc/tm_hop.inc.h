@@ -337,10 +337,12 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
     const int grp = lbl - sb * pb.ngrp;
     const int r0 = grp * NR;
     const int fl = SPLIT ? (int)(threadIdx.x & 1) : 0;  // this lane's flavour (split doublet)
-    // j: the site in processing order.  With z-chunking (pb.zc > 0) the order
-    // runs over bricks of zc consecutive z-planes of one time slice, all time
-    // slices of a chunk before the next chunk, so the two time neighbours of a
-    // site are read a few planes apart (while they can still be in L2).
+    // j: the site in processing order.  With z-chunking (pb.zc > 0) the
+    // lattice is cut into slabs of ts time slices (one XCD's share of the
+    // blocks); inside a slab the order runs over bricks of zc consecutive
+    // z-planes of one time slice, all ts slices of a brick column before the
+    // next column, so the two time neighbours of a site are read a few planes
+    // apart (while they can still be in L2).
     const uint32_t j = (uint32_t)sb * SPB + (SPLIT ? threadIdx.x >> 1 : threadIdx.x);
     const uint32_t vh = pb.vh;
     const bool valid = j < vh;
@@ -348,9 +350,12 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
     if (pb.zc > 0 && valid) {
         const uint32_t pl = (uint32_t)(pb.X[0] >> 1) * (uint32_t)pb.X[1];   // sites of an (x, y) plane
         const uint32_t brick = (uint32_t)pb.zc * pl;
-        const uint32_t q = j / brick, r = j - q * brick;
-        const uint32_t tt = q % (uint32_t)pb.X[3], ch = q / (uint32_t)pb.X[3];
-        cb = (tt * (uint32_t)pb.X[2] + ch * (uint32_t)pb.zc) * pl + r;
+        const uint32_t column = (uint32_t)pb.ts * brick;                   // ts bricks, one per slice
+        const uint32_t slab = column * (uint32_t)(pb.X[2] / pb.zc);
+        const uint32_t so = j / slab, r1 = j - so * slab;
+        const uint32_t ch = r1 / column, r2 = r1 - ch * column;
+        const uint32_t ti = r2 / brick, r = r2 - ti * brick;
+        cb = ((so * (uint32_t)pb.ts + ti) * (uint32_t)pb.X[2] + ch * (uint32_t)pb.zc) * pl + r;
     }
 
     double nrm[NR];

@@ -821,6 +821,7 @@ struct HopProblem {
     int ngrp;            // rhs groups
     int out_parity;
     int zc;              // z-planes per brick of the processing order (0: lexicographic)
+    int ts;              // time slices per slab of the processing order (zc > 0)
     double tsign;        // factor on hops across the t boundary
     Twist tw;            // twist (dagger sign folded in)
     double k;            // epilogue coefficient
