@@ -206,8 +206,9 @@ int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec
 int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, tm_prec prec,
               tm_pc pc, int dagger, int nrhs);
 
-/* out = R^-1 in (R^-+ in if dagger) on one parity (the twist is site-local and
- * uniform, so parity only selects the field size); inverse = 0 gives R, R^+.  */
+/* out = R^-1 in (R^-+ in if dagger) on one parity; inverse = 0 gives R, R^+.
+ * The twist is site-local: uniform for twisted mass, the site's clover blocks
+ * of that parity for twisted clover.                                          */
 int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
              int parity, int dagger, int inverse, int nrhs);
 int tm_twist_inv(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
@@ -280,8 +281,13 @@ int tm_convert(tm_ctx *ctx, void *dst, tm_prec dst_prec, const void *src, tm_pre
 int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm_gauge *g,
              tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev);
 
-/* Autotuner: 1 enables timing-based choice of block size per kernel and shape
- * (cached per context; persisted to $TM_TUNE_CACHE if set), 0 disables.       */
+/* Autotuner: 1 enables the timing-based choice of the hop launch per kernel
+ * variant and shape -- block size, link-load policy, cap of resident waves
+ * per SIMD, then the depth of the brick site order -- cached per context and
+ * persisted to $TM_TUNE_CACHE if set; 0 disables (defaults are then used).
+ * Read at context creation, for experiments: TM_HOP_BS, TM_LINK_NT,
+ * TM_HOP_WCAP, TM_HOP_ZC fix one of those choices, TM_XCD_REMAP=0 turns off
+ * the XCD-aware block order.                                                  */
 int tm_set_tuning(tm_ctx *ctx, int enable);
 
 #ifdef __cplusplus

@@ -69,3 +69,36 @@ def test_validation_without_device(L):
     assert L.tm_mat_pc(h, dummy, dummy, None, 0, 0, 0, 1) == -1
     assert L.tm_cg(h, dummy, dummy, None, None, None) == -1
     assert L.tm_ctx_destroy(h) == 0
+
+
+def test_validation_of_newer_entry_points_without_device(L):
+    """Twisted-clover parameters, 8-real links, full-system solves and the
+    spin basis of pack/unpack are validated before any device work."""
+    from paper_1311_4462_amd._lib import tm_cg_result, tm_params, tm_solve_params
+    h = ctypes.c_void_p()
+    assert L.tm_ctx_create(ctypes.byref(h), None) == 0
+    p = tm_params()
+    for i, d in enumerate((4, 4, 4, 4)):
+        p.dims[i] = d
+    p.kappa, p.mu, p.epsilon, p.flavor, p.t_antiperiodic = 0.16, 0.1, 0.0, 1, 1
+    g = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)
+    # recon 8 is accepted as a value; 10 is not
+    assert L.tm_gauge_create(h, ctypes.byref(g), dummy, ctypes.byref(p), 10, 3) == -1
+    # twisted clover: FP64 / FP32 only, not with 8-real links, finite c_sw
+    p.csw = 1.5
+    assert L.tm_gauge_create(h, ctypes.byref(g), dummy, ctypes.byref(p), 12, 1 << 2) == -4
+    assert L.tm_gauge_create(h, ctypes.byref(g), dummy, ctypes.byref(p), 8, 3) == -1
+    p.csw = float("inf")
+    assert L.tm_gauge_create(h, ctypes.byref(g), dummy, ctypes.byref(p), 12, 3) == -1
+    p.csw = 0.0
+    # spin basis
+    assert L.tm_spinor_pack(h, dummy, dummy, ctypes.byref(p), 0, 0, 1, 2) == -1
+    assert L.tm_spinor_unpack(h, dummy, dummy, ctypes.byref(p), 0, 0, 1, -1) == -1
+    # full-system solve: parameter checks come first
+    sp = tm_solve_params()
+    res = (tm_cg_result * 1)()
+    assert L.tm_solve(h, dummy, dummy, dummy, dummy, None, None, res) == -1
+    sp.cg.tol, sp.cg.maxiter, sp.cg.nrhs = 1e-10, 10, 1
+    assert L.tm_solve(h, dummy, dummy, dummy, dummy, None, ctypes.byref(sp), res) == -1   # null gauge
+    assert L.tm_ctx_destroy(h) == 0

@@ -146,3 +146,24 @@ def test_clover_errors(api, ctx):
         api.tm_force(ctx, F, 1, x, g, 1)
     assert e.value.code == -1
     g.close()
+
+
+def test_clover_batched_uneven_lattices(api, ctx):
+    """Two twisted-clover lattices of different size in one batched mixed solve."""
+    gs, xs, bs, ops, Us, bn = [], [], [], [], [], []
+    for i, dims in enumerate([(4, 4, 4, 8), (6, 6, 6, 6)]):
+        p, op, U, g = _setup(api, ctx, dims, 1, seed=81 + i, kind="near_unit", kappa=0.1615)
+        b = O.project(inputs.z2_spinor(dims, 1, 83 + i, nrhs=2), dims, 0)
+        gs.append(g); ops.append(op); Us.append(U); bn.append(b)
+        bs.append(to_native(api, ctx, b, p, 0, 0, 2))
+        xs.append(api.new_field(p, 0, 2))
+        ps = p
+    res = api.tm_cg_batched(ctx, gs, xs, bs, [2, 2], tol=1e-10, inner=1, pc=1)
+    assert all(r["true_rel_res_normal"] <= 1e-10 for r in res)
+    for i in range(2):
+        x = from_native(api, ctx, xs[i], gs[i].params, 0, 0, 2)
+        for r in range(2):
+            c = O.mat_pc(ops[i], Us[i], bn[i][r], "sym", dagger=True)
+            assert rel(O.normal_op(ops[i], Us[i], x[r], "sym"), c) <= 1.5e-10
+    for g in gs:
+        g.close()
