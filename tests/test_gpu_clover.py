@@ -157,7 +157,6 @@ def test_clover_batched_uneven_lattices(api, ctx):
         gs.append(g); ops.append(op); Us.append(U); bn.append(b)
         bs.append(to_native(api, ctx, b, p, 0, 0, 2))
         xs.append(api.new_field(p, 0, 2))
-        ps = p
     res = api.tm_cg_batched(ctx, gs, xs, bs, [2, 2], tol=1e-10, inner=1, pc=1)
     assert all(r["true_rel_res_normal"] <= 1e-10 for r in res)
     for i in range(2):
