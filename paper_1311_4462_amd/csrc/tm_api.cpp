@@ -463,30 +463,49 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             hipEvent_t e0, e1;
             TM_HIP(ctx, hipEventCreate(&e0));
             TM_HIP(ctx, hipEventCreate(&e1));
-            float best = 1e30f;
-            auto trial = [&](const HopCfg &c) -> int {
+            // each trial: one untimed launch, then `reps` timed back to back
+            auto trial = [&](const HopCfg &c, int reps, float *ms_per) -> int {
                 HopBatch B;
                 TM_TRY(build_hop_batch(ctx, calls, n, nr, c.bs, &B, c.zc));
                 TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
-                for (int r = 0; r < 4; r++)
+                for (int r = 0; r < reps; r++)
                     TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e1, ctx->stream));
                 TM_HIP(ctx, hipEventSynchronize(e1));
                 float ms = 0.f;
                 TM_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
-                    best = ms;
-                    cfg = c;
-                }
+                *ms_per = ms / reps;
                 return TM_OK;
             };
-            for (const HopCfg &c : cand) TM_TRY(trial(c));
+            // stage 1: every candidate briefly; the four fastest again, longer
+            std::vector<std::pair<float, HopCfg>> t1;
+            for (const HopCfg &c : cand) {
+                float ms;
+                TM_TRY(trial(c, 4, &ms));
+                t1.push_back({ms, c});
+            }
+            std::sort(t1.begin(), t1.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+            float best = 1e30f;
+            for (size_t i = 0; i < std::min<size_t>(4, t1.size()); i++) {
+                float ms;
+                TM_TRY(trial(t1[i].second, 10, &ms));
+                if (ms < best) {
+                    best = ms;
+                    cfg = t1[i].second;
+                }
+            }
+            // stage 2: brick depth of the site order for the winner
             const HopCfg base = cfg;
             for (int z : {8, 4, 2}) {
                 HopCfg c = base;
                 c.zc = z;
-                TM_TRY(trial(c));
+                float ms;
+                TM_TRY(trial(c, 10, &ms));
+                if (ms < best) {
+                    best = ms;
+                    cfg = c;
+                }
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
