@@ -435,6 +435,14 @@ def main():
         extra["batched"] = batched_section(torch, api, inputs)
         extra.update(force_section(torch, api, inputs))
 
+    # context only (another machine): the paper's single-GPU Gflops for this
+    # operator at 32^3x64 on a GTX Titan, as its abstract quotes them from
+    # Table 1 (double / single / half; 8-real links for the degenerate single
+    # and half figures)
+    extra["paper_context_gflops_32x32x32x64"] = {
+        "degenerate": {"double": 190, "single": 487, "half": 856},
+        "non_degenerate": {"double": 163, "single": 516, "half": 879},
+        "hardware": "NVIDIA GTX Titan (Kepler)"}
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gflop/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(dt * 1e3, 5),
