@@ -38,6 +38,7 @@ struct tm_ctx {
     int force_lnt = -1;                // TM_LINK_NT: 1 / 0 fixes the link load policy
     int force_zc = -1;                 // TM_HOP_ZC: fixed brick depth of the site order (0: lexicographic)
     int force_wcap = -1;               // TM_HOP_WCAP: fixed cap of resident waves per SIMD (0: none)
+    int force_ldss = -1;               // TM_HOP_LDS: 1 / 0 forces the LDS-staged variant where it exists
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
 };
@@ -238,6 +239,7 @@ struct HopCfg {
     bool lnt;
     int wcap;
     int zc = 0;     // z-planes per brick of the site order (0: lexicographic)
+    bool ldss = false;   // x / y neighbours staged in LDS (FP32, one flavour, one rhs)
 };
 // bricks of at most `target` z-planes: the largest divisor of Lz below Lz
 int zc_for(int target, int Lz)
@@ -253,7 +255,7 @@ unsigned hop_lds_bytes(const HopCfg &c)
     const unsigned blocks = std::max(1u, (unsigned)(4 * c.wcap * 64 / c.bs));   // per compute unit
     return ((kLdsPerCU / blocks) + 511u) & ~511u;
 }
-std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon, bool clv)
+std::vector<HopCfg> cfg_candidates(int prec, int nf, int nr, int twl, int recon, bool clv)
 {
     if (twl) return {{256, true, 0}};
     std::vector<int> bss = (recon == 18) ? std::vector<int>{256}
@@ -265,6 +267,13 @@ std::vector<HopCfg> cfg_candidates(int nr, int twl, int recon, bool clv)
             out.push_back({b, true, w});
             out.push_back({b, false, w});
         }
+    // LDS-staged x / y neighbours: FP32, one flavour, one rhs, 12-real links
+    if (prec == TM_FP32 && nf == 1 && nr == 1 && recon == 12 && !clv)
+        for (int b : {64, 256})
+            for (int w : {0, 3, 2}) {
+                out.push_back({b, true, w, 0, true});
+                out.push_back({b, false, w, 0, true});
+            }
     return out;
 }
 
@@ -312,12 +321,18 @@ void load_tune(tm_ctx *ctx)
 hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger, int twl, int recon,
                         const HopCfg &c, bool clv, hipStream_t st)
 {
-    const unsigned lds = hop_lds_bytes(c);
+    unsigned lds = hop_lds_bytes(c);
+    if (c.ldss) {
+        // six FP32 chunk rows of the block's sites and one y-row either side
+        int row = 0;
+        for (int i = 0; i < B.nprob; i++) row = std::max(row, B.p[i].X[0] / 2);
+        lds = std::max(lds, (unsigned)(6 * (c.bs + 2 * row) * 16));
+    }
     switch (prec) {
-    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
-    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
-    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
-    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, st);
+    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
+    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
+    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
+    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
     }
     return hipErrorInvalidValue;
 }
@@ -433,7 +448,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     for (int i = 0; i < n; i++) nr = std::min(nr, choose_nr(prec, nf, calls[i].nrhs, recon));
     for (int i = 0; i < n; i++)
         if (calls[i].nrhs % nr || clv) nr = 1;
-    const std::vector<HopCfg> cand = cfg_candidates(nr, twl, recon, clv);
+    const std::vector<HopCfg> cand = cfg_candidates(prec, nf, nr, twl, recon, clv);
     long vh_total = 0;
     size_t wset = 0;
     for (int i = 0; i < n; i++) {
@@ -451,7 +466,8 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             if (c.bs == want.bs && c.lnt == want.lnt && c.wcap == 0) cfg = want;
     } else if (it != ctx->tuned.end()) {
         const int code = it->second;
-        cfg = HopCfg{code & 0xffff, ((code >> 16) & 1) != 0, (code >> 20) & 0xf, (code >> 24) & 0x7f};
+        cfg = HopCfg{code & 0xffff, ((code >> 16) & 1) != 0, (code >> 20) & 0xf, (code >> 24) & 0x7f,
+                     ((code >> 17) & 1) != 0};
     } else if (ctx->tuning && cand.size() > 1) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(ctx->stream, &cs);
@@ -495,9 +511,11 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
                     cfg = t1[i].second;
                 }
             }
-            // stage 2: brick depth of the site order for the winner
+            // stage 2: brick depth of the site order for the winner (the
+            // LDS-staged variant needs the lexicographic order)
             const HopCfg base = cfg;
             for (int z : {8, 4, 2}) {
+                if (base.ldss) break;
                 HopCfg c = base;
                 c.zc = z;
                 float ms;
@@ -509,12 +527,17 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0) | (cfg.wcap << 20) | (cfg.zc << 24);
+            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0) | (cfg.ldss ? 1 << 17 : 0) | (cfg.wcap << 20) |
+                             (cfg.zc << 24);
             ctx->tuned[key] = code;
             save_tune(ctx, key, code);
         }
     }
     if (ctx->force_zc >= 0) cfg.zc = ctx->force_zc;
+    if (ctx->force_ldss >= 0 && (ctx->force_ldss == 0 || (prec == TM_FP32 && nf == 1 && nr == 1 &&
+                                                            recon == 12 && !clv && !twl)))
+        cfg.ldss = ctx->force_ldss != 0;
+    if (cfg.ldss) cfg.zc = 0;
     if (ctx->force_wcap >= 0) cfg.wcap = ctx->force_wcap;
     HopBatch B;
     TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B, cfg.zc));
@@ -699,6 +722,8 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (e) c->force_lnt = atoi(e) ? 1 : 0;
     e = getenv("TM_HOP_ZC");
     if (e) c->force_zc = std::max(0, atoi(e));
+    e = getenv("TM_HOP_LDS");
+    if (e) c->force_ldss = atoi(e) ? 1 : 0;
     e = getenv("TM_HOP_WCAP");
     if (e) c->force_wcap = std::min(8, std::max(0, atoi(e)));
     e = getenv("TM_TUNE");

@@ -16,7 +16,7 @@ hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t v
 
 template <int P>
 hipError_t launch_hop_prec(const HopBatch &B, int nf, int nr, int dagger, int twl, int recon,
-                           int bs, bool lnt, unsigned lds, bool clv, hipStream_t st);
+                           int bs, bool lnt, unsigned lds, bool clv, bool ldss, hipStream_t st);
 // clover blocks of both parities (FP64 and / or FP32 destinations, nullable)
 hipError_t clover_build(void *const *d64, void *const *d32, const void *links, const int *X, uint32_t vh,
                         double kc, double shift, int *bad, hipStream_t st);

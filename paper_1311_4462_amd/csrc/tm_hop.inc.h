@@ -185,10 +185,12 @@ __device__ __forceinline__ void twist_split(cx<T> (&o)[12], const cx<T> (&v)[12]
 }
 
 // One direction, forward (FWD) or backward, for all rhs and flavours.
-template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int MU, bool FWD>
+template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int MU, bool FWD,
+          bool LDSS = false>
 __device__ __forceinline__ void hop_direction(
     cx<typename Prec<P>::real> (&acc)[NR][flavours_per_thread<NF>()][12], const HopProblem &pb,
-    uint32_t nb, uint32_t link_cb, int link_par, int r0, typename Prec<P>::real sgn, int fl)
+    uint32_t nb, uint32_t link_cb, int link_par, int r0, typename Prec<P>::real sgn, int fl,
+    const float4 *lds = nullptr, uint32_t lo = 0, uint32_t span = 0)
 {
     using real = typename Prec<P>::real;
     constexpr int SIG = (FWD != DAG) ? 1 : -1;   // D: 1 - g forward; D^+ swaps
@@ -237,6 +239,22 @@ __device__ __forceinline__ void hop_direction(
             }
         }
     } else {
+        if constexpr (LDSS && MU < 2) {
+            // x and y neighbours of the block's sites come from the staged copy
+            static_assert(P == TM_FP32 && NF == 1 && NR == 1, "LDS staging: FP32, one flavour, one rhs");
+            const uint32_t o = nb - lo;
+            if (o < span) {
+                cx<real> v[12];
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    const float4 c = lds[k * span + o];
+                    v[2 * k] = mk(c.x, c.y);
+                    v[2 * k + 1] = mk(c.z, c.w);
+                }
+                hop_accumulate<MU, SIG, !FWD>(acc[0][0], u, v, sgn);
+                return;
+            }
+        }
 #pragma unroll
         for (int r = 0; r < NR; r++)
 #pragma unroll
@@ -314,7 +332,11 @@ constexpr int fence_mode()
 
 // CLV: twisted clover, the epilogue's twist is the per-site R(x) (clover
 // blocks of the output parity); twist-on-load is not combined with it.
-template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int BS, bool CLV = false>
+// LDSS: the input spinors of the block's sites and of one y-row either side
+// are staged in LDS (FP32, one flavour, one rhs, lexicographic site order);
+// x and y neighbours are then read from there.
+template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int BS, bool CLV = false,
+          bool LDSS = false>
 __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(const HopBatch B)
 {
     using real = typename Prec<P>::real;
@@ -347,6 +369,24 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
     const uint32_t vh = pb.vh;
     const bool valid = j < vh;
     uint32_t cb = j;
+    [[maybe_unused]] uint32_t st_lo = 0, st_span = 0;
+    [[maybe_unused]] extern __shared__ float4 st_lds[];
+    if constexpr (LDSS) {
+        // every thread takes part in staging (lexicographic order: the block's
+        // sites are the contiguous range [sb * BS, sb * BS + BS))
+        const uint32_t row = (uint32_t)(pb.X[0] >> 1);
+        const uint32_t b0 = (uint32_t)sb * BS;
+        st_lo = b0 > row ? b0 - row : 0;
+        const uint32_t hi = min(vh, b0 + BS + row);
+        st_span = hi > st_lo ? hi - st_lo : 0;
+        const uint32_t span_max = BS + 2 * row;
+        for (uint32_t k = 0; k < 6; k++) {
+            const float4 *src = (const float4 *)((const char *)pb.in.data + (size_t)k * vh * 16);
+            for (uint32_t o = threadIdx.x; o < span_max; o += BS)
+                if (o < st_span) st_lds[k * st_span + o] = src[st_lo + o];
+        }
+        __syncthreads();
+    }
     if (pb.zc > 0 && valid) {
         const uint32_t pl = (uint32_t)(pb.X[0] >> 1) * (uint32_t)pb.X[1];   // sites of an (x, y) plane
         const uint32_t brick = (uint32_t)pb.zc * pl;
@@ -391,27 +431,27 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
             const int xp = (x + 1 == Lx) ? 0 : x + 1;
             const int xm = (x == 0) ? Lx - 1 : x - 1;
             const uint32_t nf_ = base + (xp >> 1), nb_ = base + (xm >> 1);
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, true>(acc, pb, nf_, cb, par, r0, one, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, true, LDSS>(acc, pb, nf_, cb, par, r0, one, fl, st_lds, st_lo, st_span);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, false>(acc, pb, nb_, nb_, npar, r0, one, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 0, false, LDSS>(acc, pb, nb_, nb_, npar, r0, one, fl, st_lds, st_lo, st_span);
             TM_DIR_FENCE();
         }
         // y direction
         {
             const uint32_t nf_ = (y == Ly - 1) ? cb - (uint32_t)(Ly - 1) * sy : cb + sy;
             const uint32_t nb_ = (y == 0) ? cb + (uint32_t)(Ly - 1) * sy : cb - sy;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, true>(acc, pb, nf_, cb, par, r0, one, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, true, LDSS>(acc, pb, nf_, cb, par, r0, one, fl, st_lds, st_lo, st_span);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, false>(acc, pb, nb_, nb_, npar, r0, one, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 1, false, LDSS>(acc, pb, nb_, nb_, npar, r0, one, fl, st_lds, st_lo, st_span);
             TM_DIR_FENCE();
         }
         // z direction
         {
             const uint32_t nf_ = (z == Lz - 1) ? cb - (uint32_t)(Lz - 1) * sz : cb + sz;
             const uint32_t nb_ = (z == 0) ? cb + (uint32_t)(Lz - 1) * sz : cb - sz;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, true>(acc, pb, nf_, cb, par, r0, one, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, true, LDSS>(acc, pb, nf_, cb, par, r0, one, fl, st_lds, st_lo, st_span);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, false>(acc, pb, nb_, nb_, npar, r0, one, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 2, false, LDSS>(acc, pb, nb_, nb_, npar, r0, one, fl, st_lds, st_lo, st_span);
             TM_DIR_FENCE();
         }
         // t direction (boundary factor on hops across t = Lt-1 <-> 0)
@@ -420,9 +460,9 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
             const uint32_t nb_ = (t == 0) ? cb + (uint32_t)(Lt - 1) * st : cb - st;
             const real sf = (t == Lt - 1) ? (real)pb.tsign : one;
             const real sbk = (t == 0) ? (real)pb.tsign : one;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, true>(acc, pb, nf_, cb, par, r0, sf, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, true, LDSS>(acc, pb, nf_, cb, par, r0, sf, fl, st_lds, st_lo, st_span);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, false>(acc, pb, nb_, nb_, npar, r0, sbk, fl);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, false, LDSS>(acc, pb, nb_, nb_, npar, r0, sbk, fl, st_lds, st_lo, st_span);
             TM_DIR_FENCE();
         }
 
@@ -516,7 +556,7 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
 // Host-side dispatch over the compile-time variants built for precision P.
 
 #define TM_HOP_CASE(P, NF, NR, DAG, TWL, RECON, LNT, BS)                                          \
-    if (!clv && nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON &&           \
+    if (!clv && !ldss && nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON &&  \
         lnt == LNT && bs == BS) {                                                                   \
         hipLaunchKernelGGL((hop_kernel<P, NF, NR, DAG, TWL, RECON, LNT, BS>), dim3(B.total_blocks), \
                            dim3(BS), lds, st, B);                                                   \
@@ -531,6 +571,18 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
                            dim3(B.total_blocks), dim3(BS), lds, st, B);                             \
         return hipGetLastError();                                                                   \
     }
+// LDS-staged x / y neighbours (FP32, one flavour, one rhs, 12-real links)
+#define TM_HOP_CASE_LDSS(P, DAG, LNT, BS)                                                          \
+    if (ldss && !clv && nf == 1 && nr == 1 && dagger == DAG && twl == 0 && recon == 12 &&          \
+        lnt == LNT && bs == BS) {                                                                   \
+        hipLaunchKernelGGL((hop_kernel<P, 1, 1, DAG, false, 12, LNT, BS, false, true>),             \
+                           dim3(B.total_blocks), dim3(BS), lds, st, B);                             \
+        return hipGetLastError();                                                                   \
+    }
+#define TM_HOP_CASES_LDSS(P, BS)                                               \
+    TM_HOP_CASE_LDSS(P, 0, true, BS) TM_HOP_CASE_LDSS(P, 1, true, BS)          \
+    TM_HOP_CASE_LDSS(P, 0, false, BS) TM_HOP_CASE_LDSS(P, 1, false, BS)
+
 #define TM_HOP_CASES_CLV(P, NF, RECON, BS)               \
     TM_HOP_CASE_CLV(P, NF, 0, RECON, true, BS)           \
     TM_HOP_CASE_CLV(P, NF, 1, RECON, true, BS)           \
@@ -553,8 +605,12 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
     template <>                                                                                \
     hipError_t launch_hop_prec<P>(const HopBatch &B, int nf, int nr, int dagger, int twl,      \
                                   int recon, int bs, bool lnt, unsigned lds, bool clv,         \
-                                  hipStream_t st)                                              \
+                                  bool ldss, hipStream_t st)                                   \
     {                                                                                          \
+        if constexpr (P == TM_FP32) {                                                          \
+            TM_HOP_CASES_LDSS(P, 256)                                                          \
+            TM_HOP_CASES_LDSS(P, 64)                                                           \
+        }                                                                                      \
         if constexpr (P == TM_FP64 || P == TM_FP32) {                                          \
             TM_HOP_CASES_CLV(P, 1, 12, 256)                                                    \
             TM_HOP_CASES_CLV(P, 1, 12, 64)                                                     \

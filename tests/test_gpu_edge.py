@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1311_4462_amd import inputs
-from tests.gpu_util import TOL, from_native, oparams, rel, to_native
+from tests.gpu_util import TOL, from_native, oparams, oracle_dslash, rel, to_native
 
 pytestmark = pytest.mark.gpu
 
@@ -139,6 +139,42 @@ def test_brick_site_order(api, zc, monkeypatch):
                     api.tm_mat_pc(c, out, t, g, prec, pc, dag)
                     ref = O.mat_pc(op, U, x, "asym" if pc == 0 else "sym", bool(dag))
                     assert rel(from_native(api, c, out, p, prec, 0)[0], ref) < TOL[prec]
+        tx = api.new_field(p, 0)
+        r = api.tm_cg(c, tx, to_native(api, c, x, p, 0, 0), g, tol=1e-10, inner=1)[0]
+        assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
+        g.close()
+    c.close()
+
+
+def test_lds_staged_neighbours(api, monkeypatch):
+    """The FP32 one-flavour variant that stages x / y neighbours in LDS (rows
+    wrapping in y and a ragged last block read from global memory): every
+    epilogue, both daggers, the preconditioned operators and a mixed solve."""
+    monkeypatch.setenv("TM_HOP_LDS", "1")
+    c = api.Context()
+    for dims in ((8, 6, 4, 10), (6, 4, 4, 6), (24, 2, 2, 4)):
+        p = api.make_params(dims, 0.16, 0.13, 0.0, 1)
+        op = oparams(p)
+        U = inputs.gauge_field(dims, "haar", 97)
+        g = api.Gauge(c, U, p, precs=(0, 1))
+        for outp in (0, 1):
+            inp = O.project(inputs.gaussian_spinor(dims, 1, 98), dims, 1 - outp)
+            xv = O.project(inputs.gaussian_spinor(dims, 1, 99), dims, outp)
+            ti, tx = to_native(api, c, inp, p, 1, 1 - outp), to_native(api, c, xv, p, 1, outp)
+            out = api.new_field(p, 1)
+            for epi in range(6):
+                for dag in (0, 1):
+                    api.tm_dslash(c, out, ti, g, 1, outp, dag, 0, epi, tx, -0.37)
+                    ref = oracle_dslash(op, U, inp, outp, dag, 0, epi, xv, -0.37)
+                    assert rel(from_native(api, c, out, p, 1, outp)[0], ref) < TOL[1], (dims, epi, dag)
+        x = O.project(inputs.gaussian_spinor(dims, 1, 100), dims, 0)
+        t = to_native(api, c, x, p, 1, 0)
+        out = api.new_field(p, 1)
+        for pc in (0, 1):
+            for dag in (0, 1):
+                api.tm_mat_pc(c, out, t, g, 1, pc, dag)
+                ref = O.mat_pc(op, U, x, "asym" if pc == 0 else "sym", bool(dag))
+                assert rel(from_native(api, c, out, p, 1, 0)[0], ref) < TOL[1]
         tx = api.new_field(p, 0)
         r = api.tm_cg(c, tx, to_native(api, c, x, p, 0, 0), g, tol=1e-10, inner=1)[0]
         assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
