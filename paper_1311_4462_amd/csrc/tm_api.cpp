@@ -475,7 +475,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             // time the instantiated configurations on the real launch (hop
             // launches are idempotent: out never aliases an input): block size
             // x link-load policy x wave cap in lexicographic site order, then
-            // the site order's brick depth for the best of those
+            // the four best of those with each brick depth of the site order
             hipEvent_t e0, e1;
             TM_HIP(ctx, hipEventCreate(&e0));
             TM_HIP(ctx, hipEventCreate(&e1));
@@ -494,7 +494,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
                 *ms_per = ms / reps;
                 return TM_OK;
             };
-            // stage 1: every candidate briefly; the four fastest again, longer
+            // stage 1: every candidate briefly, lexicographic site order
             std::vector<std::pair<float, HopCfg>> t1;
             for (const HopCfg &c : cand) {
                 float ms;
@@ -502,29 +502,27 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
                 t1.push_back({ms, c});
             }
             std::sort(t1.begin(), t1.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+            // stage 2: the four fastest, each in lexicographic order and in
+            // bricks of 8, 4 and 2 z-planes (the LDS-staged variant needs the
+            // lexicographic order), timed longer: the best of three batches
+            // of eight launches, which is less sensitive to clock changes
             float best = 1e30f;
-            for (size_t i = 0; i < std::min<size_t>(4, t1.size()); i++) {
-                float ms;
-                TM_TRY(trial(t1[i].second, 10, &ms));
-                if (ms < best) {
-                    best = ms;
-                    cfg = t1[i].second;
+            for (size_t i = 0; i < std::min<size_t>(4, t1.size()); i++)
+                for (int z : {0, 8, 4, 2}) {
+                    HopCfg c = t1[i].second;
+                    if (z && c.ldss) break;
+                    c.zc = z;
+                    float ms = 1e30f;
+                    for (int rep = 0; rep < 3; rep++) {
+                        float m;
+                        TM_TRY(trial(c, 8, &m));
+                        ms = std::min(ms, m);
+                    }
+                    if (ms < best) {
+                        best = ms;
+                        cfg = c;
+                    }
                 }
-            }
-            // stage 2: brick depth of the site order for the winner (the
-            // LDS-staged variant needs the lexicographic order)
-            const HopCfg base = cfg;
-            for (int z : {8, 4, 2}) {
-                if (base.ldss) break;
-                HopCfg c = base;
-                c.zc = z;
-                float ms;
-                TM_TRY(trial(c, 10, &ms));
-                if (ms < best) {
-                    best = ms;
-                    cfg = c;
-                }
-            }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0) | (cfg.ldss ? 1 << 17 : 0) | (cfg.wcap << 20) |

@@ -68,18 +68,13 @@ __device__ __forceinline__ cx<T> link_row(const cx<T> (&u)[3][3], const cx<T> (&
     return mk(re, im);
 }
 
-// Project, multiply by the link and accumulate one hop.
-//   SIG = +1: projector (1 - g_mu);  SIG = -1: projector (1 + g_mu)
-//   BWD: use U^+ (backward hop) instead of U.
-// The link products are FMA chains and the hop's factor (boundary sign,
-// and 2 for the time projector) enters through the accumulating FMAs.
-template <int MU, int SIG, bool BWD, typename T>
-__device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u)[3][3],
-                                               const cx<T> *v, T sgn)
+// Spin projection of the neighbour v to the half spinor h:
+//   SIG = +1: projector (1 - g_mu);  SIG = -1: projector (1 + g_mu).
+// v holds the 12 elements of the neighbour (or, for MU == 3, only the 6
+// elements of the spin pair the projector keeps, at v[0..5]).
+template <int MU, int SIG, typename T>
+__device__ __forceinline__ void project(cx<T> (&h)[2][3], const cx<T> *v)
 {
-    // v holds the 12 elements of the neighbour (or, for MU == 3, only the 6
-    // elements of the spin pair the projector keeps, at v[0..5]).
-    cx<T> h[2][3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if constexpr (MU == 0) {          // i s_1 psiL = (i psi3, i psi2)
@@ -111,11 +106,110 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
             h[1][c] = v[3 + c];
         }
     }
+}
+
+// a + s b of two binary16 values, each the low (L = 0) or high (L = 1) half
+// of a 32-bit word, in one FP32 fused multiply-add with binary16 sources
+// (exact products, one rounding: the FP32 sum of the converted values).
+template <int LA, int LB, bool NEG>
+__device__ __forceinline__ float mix_add(uint32_t a, uint32_t b)
+{
+    float d;
+#define TM_MIX(SA, SB, N)                                                                              \
+    __asm__("v_fma_mix_f32 %0, %1, 1.0, " N "%2 op_sel:[" #SA ",0," #SB "] op_sel_hi:[1,0,1]" \
+            : "=v"(d)                                                                              \
+            : "v"(a), "v"(b))
+    if constexpr (!NEG) {
+        if constexpr (LA == 0 && LB == 0) TM_MIX(0, 0, "");
+        else if constexpr (LA == 0 && LB == 1) TM_MIX(0, 1, "");
+        else if constexpr (LA == 1 && LB == 0) TM_MIX(1, 0, "");
+        else TM_MIX(1, 1, "");
+    } else {
+        if constexpr (LA == 0 && LB == 0) TM_MIX(0, 0, "-");
+        else if constexpr (LA == 0 && LB == 1) TM_MIX(0, 1, "-");
+        else if constexpr (LA == 1 && LB == 0) TM_MIX(1, 0, "-");
+        else TM_MIX(1, 1, "-");
+    }
+#undef TM_MIX
+    return d;
+}
+
+// Complex a + k b of two binary16 complex words (real part low, imaginary
+// high) with k = +1 (K = 0), -1 (K = 1), +i (K = 2) or -i (K = 3).
+template <int K>
+__device__ __forceinline__ cx<float> mix_cadd(uint32_t a, uint32_t b)
+{
+    if constexpr (K == 0) return mk(mix_add<0, 0, false>(a, b), mix_add<1, 1, false>(a, b));
+    else if constexpr (K == 1) return mk(mix_add<0, 0, true>(a, b), mix_add<1, 1, true>(a, b));
+    else if constexpr (K == 2) return mk(mix_add<0, 1, true>(a, b), mix_add<1, 0, false>(a, b));
+    else return mk(mix_add<0, 1, false>(a, b), mix_add<1, 0, true>(a, b));
+}
+
+// project() for a half-precision neighbour given as stored words (without
+// its site scale): binary16 through mix_cadd, bfloat16 converted first.
+template <int P, int MU, int SIG>
+__device__ __forceinline__ void project_words(cx<float> (&h)[2][3], const uint32_t *w)
+{
+    auto cadd = [](auto kk, uint32_t a, uint32_t b) {
+        constexpr int K = decltype(kk)::value;
+        if constexpr (P == TM_FP16) {
+            return mix_cadd<K>(a, b);
+        } else {
+            const cx<float> x = mk(b2f((uint16_t)(a & 0xffff)), b2f((uint16_t)(a >> 16)));
+            const cx<float> y = mk(b2f((uint16_t)(b & 0xffff)), b2f((uint16_t)(b >> 16)));
+            if constexpr (K == 0) return x + y;
+            else if constexpr (K == 1) return x - y;
+            else if constexpr (K == 2) return x + times_i(y);
+            else return x + times_mi(y);
+        }
+    };
+    using k0 = std::integral_constant<int, 0>;
+    using k1 = std::integral_constant<int, 1>;
+    using k2 = std::integral_constant<int, 2>;
+    using k3 = std::integral_constant<int, 3>;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 0) {
+            if constexpr (SIG > 0) {
+                h[0][c] = cadd(k3{}, w[c], w[9 + c]);
+                h[1][c] = cadd(k3{}, w[3 + c], w[6 + c]);
+            } else {
+                h[0][c] = cadd(k2{}, w[c], w[9 + c]);
+                h[1][c] = cadd(k2{}, w[3 + c], w[6 + c]);
+            }
+        } else if constexpr (MU == 1) {
+            if constexpr (SIG > 0) {
+                h[0][c] = cadd(k1{}, w[c], w[9 + c]);
+                h[1][c] = cadd(k0{}, w[3 + c], w[6 + c]);
+            } else {
+                h[0][c] = cadd(k0{}, w[c], w[9 + c]);
+                h[1][c] = cadd(k1{}, w[3 + c], w[6 + c]);
+            }
+        } else if constexpr (MU == 2) {
+            if constexpr (SIG > 0) {
+                h[0][c] = cadd(k3{}, w[c], w[6 + c]);
+                h[1][c] = cadd(k2{}, w[3 + c], w[9 + c]);
+            } else {
+                h[0][c] = cadd(k2{}, w[c], w[6 + c]);
+                h[1][c] = cadd(k3{}, w[3 + c], w[9 + c]);
+            }
+        } else {
+            h[0][c] = mk(half_to_f<P>((uint16_t)(w[c] & 0xffff)), half_to_f<P>((uint16_t)(w[c] >> 16)));
+            h[1][c] = mk(half_to_f<P>((uint16_t)(w[3 + c] & 0xffff)), half_to_f<P>((uint16_t)(w[3 + c] >> 16)));
+        }
+    }
+}
+
+// Rebuild the lower spin pair from the six link products g[s][c] (s: row of
+// the half spinor, c: colour) and accumulate with the factor sgn (boundary
+// sign, and 2 for the time projector) through the accumulating FMAs.
+template <int MU, int SIG, typename T>
+__device__ __forceinline__ void accumulate_hop(cx<T> (&acc)[12], const cx<T> (&g)[2][3], T sgn)
+{
     const T f = (MU == 3) ? (T)2 * sgn : sgn;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        const cx<T> g0 = link_row<BWD>(u, h[0], c);
-        const cx<T> g1 = link_row<BWD>(u, h[1], c);
+        const cx<T> g0 = g[0][c], g1 = g[1][c];
         if constexpr (MU == 3) {
             if constexpr (SIG > 0) {
                 acc_k<0>(acc[6 + c], f, g0);
@@ -140,6 +234,195 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
             }
         }
     }
+}
+
+// Multiply the half spinor by the link (BWD: by U^+) as FMA chains and
+// accumulate.
+template <int MU, int SIG, bool BWD, typename T>
+__device__ __forceinline__ void mul_accumulate(cx<T> (&acc)[12], const cx<T> (&u)[3][3],
+                                               const cx<T> (&h)[2][3], T sgn)
+{
+    cx<T> g[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        g[0][c] = link_row<BWD>(u, h[0], c);
+        g[1][c] = link_row<BWD>(u, h[1], c);
+    }
+    accumulate_hop<MU, SIG>(acc, g, sgn);
+}
+
+// ---- binary16: projection and link products on packed pairs
+//
+// The projected half spinor h is rounded once to binary16 (the precision the
+// neighbour is stored in) and each real part of a link product becomes three
+// two-term dot products with FP32 accumulation (binary16 products are exact
+// in FP32):
+//   U h:   re = sum_b u_ab . (h.re, -h.im),  im = sum_b u_ab . (h.im,  h.re)
+//   U^+ h: re = sum_b u_ba . (h.re,  h.im),  im = sum_b u_ba . (h.im, -h.re)
+// The two pairs each product needs, p = (h.re, +-h.im) and s = (h.im, +-h.re),
+// come straight from the stored words, one packed addition each.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// h = a + k b of two stored words (k = +1, -1, +i, -i for K = 0..3):
+//   p = (h.re, -h.im) if BWD is false, else (h.re, h.im);
+//   s = (h.im, h.re) if BWD is false, else (h.im, -h.re).
+// Each is one packed addition with per-lane operand halves (op_sel: low
+// lane, op_sel_hi: high lane) and per-lane signs of the operands.
+template <int K, bool BWD>
+__device__ __forceinline__ void pair_cadd(f16x2 &p, f16x2 &s, uint32_t a, uint32_t b)
+{
+    uint32_t x, y;
+#define TM_PK(D, MODS) __asm__("v_pk_add_f16 %0, %1, %2 " MODS : "=v"(D) : "v"(a), "v"(b))
+    if constexpr (K == 0) {          // h = (a.re + b.re, a.im + b.im)
+        if constexpr (!BWD) {
+            TM_PK(x, "neg_hi:[1,1]");
+            TM_PK(y, "op_sel:[1,1] op_sel_hi:[0,0]");
+        } else {
+            TM_PK(x, "");
+            TM_PK(y, "op_sel:[1,1] op_sel_hi:[0,0] neg_hi:[1,1]");
+        }
+    } else if constexpr (K == 1) {   // h = (a.re - b.re, a.im - b.im)
+        if constexpr (!BWD) {
+            TM_PK(x, "neg_lo:[0,1] neg_hi:[1,0]");
+            TM_PK(y, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[0,1]");
+        } else {
+            TM_PK(x, "neg_lo:[0,1] neg_hi:[0,1]");
+            TM_PK(y, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[1,0]");
+        }
+    } else if constexpr (K == 2) {   // h = (a.re - b.im, a.im + b.re)
+        if constexpr (!BWD) {
+            TM_PK(x, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[1,1]");
+            TM_PK(y, "op_sel:[1,0] op_sel_hi:[0,1] neg_hi:[0,1]");
+        } else {
+            TM_PK(x, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1]");
+            TM_PK(y, "op_sel:[1,0] op_sel_hi:[0,1] neg_hi:[1,0]");
+        }
+    } else {                         // h = (a.re + b.im, a.im - b.re)
+        if constexpr (!BWD) {
+            TM_PK(x, "op_sel:[0,1] op_sel_hi:[1,0] neg_hi:[1,0]");
+            TM_PK(y, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1]");
+        } else {
+            TM_PK(x, "op_sel:[0,1] op_sel_hi:[1,0] neg_hi:[0,1]");
+            TM_PK(y, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1] neg_hi:[1,1]");
+        }
+    }
+#undef TM_PK
+    p = __builtin_bit_cast(f16x2, x);
+    s = __builtin_bit_cast(f16x2, y);
+}
+
+template <int MU, int SIG, bool BWD>
+__device__ __forceinline__ void project_pairs(f16x2 (&hp)[2][3], f16x2 (&hs)[2][3], const uint32_t *w)
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if constexpr (MU == 0) {
+            pair_cadd<(SIG > 0 ? 3 : 2), BWD>(hp[0][c], hs[0][c], w[c], w[9 + c]);
+            pair_cadd<(SIG > 0 ? 3 : 2), BWD>(hp[1][c], hs[1][c], w[3 + c], w[6 + c]);
+        } else if constexpr (MU == 1) {
+            pair_cadd<(SIG > 0 ? 1 : 0), BWD>(hp[0][c], hs[0][c], w[c], w[9 + c]);
+            pair_cadd<(SIG > 0 ? 0 : 1), BWD>(hp[1][c], hs[1][c], w[3 + c], w[6 + c]);
+        } else if constexpr (MU == 2) {
+            pair_cadd<(SIG > 0 ? 3 : 2), BWD>(hp[0][c], hs[0][c], w[c], w[6 + c]);
+            pair_cadd<(SIG > 0 ? 2 : 3), BWD>(hp[1][c], hs[1][c], w[3 + c], w[9 + c]);
+        } else {
+            // time: h is the stored spin pair; sign flips and the swap are
+            // bit operations on the word
+#pragma unroll
+            for (int r = 0; r < 2; r++) {
+                const uint32_t v = w[3 * r + c];
+                const uint32_t sw = (v >> 16) | (v << 16);
+                hp[r][c] = __builtin_bit_cast(f16x2, BWD ? v : v ^ 0x80000000u);
+                hs[r][c] = __builtin_bit_cast(f16x2, BWD ? sw ^ 0x80000000u : sw);
+            }
+        }
+    }
+}
+
+// d = u . v + c with FP32 accumulation.  Written with the compiler's builtin
+// so that the wait states a dot product's result needs before another VALU
+// instruction reads it are inserted.
+__device__ __forceinline__ float dot2_acc(f16x2 u, f16x2 v, float c)
+{
+    return __builtin_amdgcn_fdot2(u, v, c, false);
+}
+
+// Row a of U h (BWD: of U^+ h) from the pairs of pair_cadd.
+template <bool BWD>
+__device__ __forceinline__ cx<float> link_row_pairs(const f16x2 (&u)[3][3], const f16x2 (&hp)[3],
+                                                    const f16x2 (&hs)[3], int a)
+{
+    float re = dot2_acc(BWD ? u[0][a] : u[a][0], hp[0], 0.f);
+    float im = dot2_acc(BWD ? u[0][a] : u[a][0], hs[0], 0.f);
+#pragma unroll
+    for (int b = 1; b < 3; b++) {
+        re = dot2_acc(BWD ? u[b][a] : u[a][b], hp[b], re);
+        im = dot2_acc(BWD ? u[b][a] : u[a][b], hs[b], im);
+    }
+    return mk(re, im);
+}
+
+// Project, multiply by the link and accumulate one hop (BWD: U^+).
+template <int MU, int SIG, bool BWD, typename T>
+__device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u)[3][3],
+                                               const cx<T> *v, T sgn)
+{
+    cx<T> h[2][3];
+    project<MU, SIG>(h, v);
+    mul_accumulate<MU, SIG, BWD>(acc, u, h, sgn);
+}
+
+// Load the neighbour vector vec at site nb for a hop in direction MU and
+// accumulate it (the half-precision site scale enters with the hop's factor;
+// half-precision values are converted inside the projection's additions).
+template <int P, int MU, int SIG, bool BWD>
+__device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
+                                         const cx<typename Prec<P>::real> (&u)[3][3], const SpinorPtr &in,
+                                         uint32_t vh, uint32_t vec, uint32_t nb, typename Prec<P>::real sgn)
+{
+    using real = typename Prec<P>::real;
+    real sc;
+    cx<real> h[2][3];
+    if constexpr (P == TM_FP16 || P == TM_BF16) {
+        uint32_t w[12];
+        if constexpr (MU == 3) {
+            if constexpr (SIG > 0)
+                SpinorIO<P>::template load_words<6, 6>(w, in, vh, vec, nb, sc);
+            else
+                SpinorIO<P>::template load_words<0, 6>(w, in, vh, vec, nb, sc);
+        } else {
+            SpinorIO<P>::template load_words<0, 12>(w, in, vh, vec, nb, sc);
+        }
+        if constexpr (P == TM_FP16 && kF16Pairs) {
+            f16x2 hp[2][3], hs[2][3], u2[3][3];
+            project_pairs<MU, SIG, BWD>(hp, hs, w);
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int b = 0; b < 3; b++) u2[a][b] = (f16x2){(_Float16)u[a][b].re, (_Float16)u[a][b].im};
+            cx<float> g[2][3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                g[0][c] = link_row_pairs<BWD>(u2, hp[0], hs[0], c);
+                g[1][c] = link_row_pairs<BWD>(u2, hp[1], hs[1], c);
+            }
+            accumulate_hop<MU, SIG>(acc, g, sgn * sc);
+            return;
+        }
+        project_words<P, MU, SIG>(h, w);
+    } else {
+        cx<real> v[12];
+        if constexpr (MU == 3) {
+            if constexpr (SIG > 0)
+                SpinorIO<P>::template load_unscaled<6, 6>(v, in, vh, vec, nb, sc);
+            else
+                SpinorIO<P>::template load_unscaled<0, 6>(v, in, vh, vec, nb, sc);
+        } else {
+            SpinorIO<P>::template load_unscaled<0, 12>(v, in, vh, vec, nb, sc);
+        }
+        project<MU, SIG>(h, v);
+    }
+    mul_accumulate<MU, SIG, BWD>(acc, u, h, sgn * sc);
 }
 
 // Doublet sites are split over lane pairs: lane 2k holds flavour 0 and lane
@@ -211,15 +494,7 @@ __device__ __forceinline__ void hop_direction(
                 else
                     hop_accumulate<MU, SIG, !FWD>(acc[r][0], u, v, sgn);
             } else {
-                if constexpr (MU == 3) {
-                    if constexpr (SIG > 0)
-                        SpinorIO<P>::template load<6, 6>(v, pb.in, vh, vec, nb);
-                    else
-                        SpinorIO<P>::template load<0, 6>(v, pb.in, vh, vec, nb);
-                } else {
-                    SpinorIO<P>::template load<0, 12>(v, pb.in, vh, vec, nb);
-                }
-                hop_accumulate<MU, SIG, !FWD>(acc[r][0], u, v, sgn);
+                load_hop<P, MU, SIG, !FWD>(acc[r][0], u, pb.in, vh, vec, nb, sgn);
             }
         }
     } else if constexpr (TWL) {
@@ -259,17 +534,7 @@ __device__ __forceinline__ void hop_direction(
         for (int r = 0; r < NR; r++)
 #pragma unroll
             for (int f = 0; f < NF; f++) {
-                cx<real> v[12];
-                const uint32_t vec = (uint32_t)((r0 + r) * NF + f);
-                if constexpr (MU == 3) {
-                    if constexpr (SIG > 0)
-                        SpinorIO<P>::template load<6, 6>(v, pb.in, vh, vec, nb);
-                    else
-                        SpinorIO<P>::template load<0, 6>(v, pb.in, vh, vec, nb);
-                } else {
-                    SpinorIO<P>::template load<0, 12>(v, pb.in, vh, vec, nb);
-                }
-                hop_accumulate<MU, SIG, !FWD>(acc[r][f], u, v, sgn);
+                load_hop<P, MU, SIG, !FWD>(acc[r][f], u, pb.in, vh, (uint32_t)((r0 + r) * NF + f), nb, sgn);
             }
     }
 }

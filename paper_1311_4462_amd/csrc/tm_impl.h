@@ -19,6 +19,12 @@ constexpr int kMaxProblems = 8;   // problems per batched launch
 #define TM_ND_SPLIT 0
 #endif
 constexpr bool kNdSplit = TM_ND_SPLIT != 0;
+// Binary16 hops: projection and link products on packed binary16 pairs with
+// two-term dot products (TM_F16_PAIRS=0: FP32 arithmetic after conversion).
+#ifndef TM_F16_PAIRS
+#define TM_F16_PAIRS 1
+#endif
+constexpr bool kF16Pairs = TM_F16_PAIRS != 0;
 constexpr int kBlock = 256;       // default threads per block
 
 // ------------------------------------------------------------------ complex
@@ -214,6 +220,65 @@ struct SpinorIO {
         }
     }
 
+    // As load, but half-precision values come without the site scale, which
+    // is returned in sc (FP32 / FP64: sc = 1), so that a caller that is linear
+    // in v applies it once to its result.
+    template <int K0, int N>
+    __device__ static __forceinline__ void load_unscaled(cx<real> *v, const SpinorPtr &s, uint32_t vh,
+                                                         uint32_t vec, uint32_t cb, real &sc)
+    {
+        if constexpr (P == TM_FP64 || P == TM_FP32) {
+            load<K0, N>(v, s, vh, vec, cb);
+            sc = (real)1;
+        } else {
+            const uint32_t off = cb * CB;
+            sc = *at<float>(s.scale + (size_t)vec * vh, cb * 4u);
+            if constexpr (K0 == 0 && N == 12) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) unpack4(v + 4 * k, *at<uint4>(row(s, vh, vec, k), off), 1.0f);
+            } else if constexpr (K0 == 0 && N == 6) {
+                unpack4(v, *at<uint4>(row(s, vh, vec, 0), off), 1.0f);
+                unpack2(v + 4, *at<uint2>(row(s, vh, vec, 1), off), 1.0f);
+            } else {
+                static_assert(K0 == 6 && N == 6, "half-precision loads: full site or one spin pair");
+                unpack2(v, *at<uint2>(row(s, vh, vec, 1), off + 8u), 1.0f);
+                unpack4(v + 2, *at<uint4>(row(s, vh, vec, 2), off), 1.0f);
+            }
+        }
+    }
+
+    // Half precision: the stored words of complex elements [K0, K0 + N)
+    // (real part in the low 16 bits) and the site scale.
+    template <int K0, int N>
+    __device__ static __forceinline__ void load_words(uint32_t *w, const SpinorPtr &s, uint32_t vh,
+                                                      uint32_t vec, uint32_t cb, float &sc)
+    {
+        static_assert(P == TM_FP16 || P == TM_BF16, "stored words: half precision");
+        const uint32_t off = cb * CB;
+        sc = *at<float>(s.scale + (size_t)vec * vh, cb * 4u);
+        auto put4 = [](uint32_t *o, uint4 c) {
+            o[0] = c.x;
+            o[1] = c.y;
+            o[2] = c.z;
+            o[3] = c.w;
+        };
+        if constexpr (K0 == 0 && N == 12) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) put4(w + 4 * k, *at<uint4>(row(s, vh, vec, k), off));
+        } else if constexpr (K0 == 0 && N == 6) {
+            put4(w, *at<uint4>(row(s, vh, vec, 0), off));
+            const uint2 c = *at<uint2>(row(s, vh, vec, 1), off);
+            w[4] = c.x;
+            w[5] = c.y;
+        } else {
+            static_assert(K0 == 6 && N == 6, "half-precision loads: full site or one spin pair");
+            const uint2 c = *at<uint2>(row(s, vh, vec, 1), off + 8u);
+            w[0] = c.x;
+            w[1] = c.y;
+            put4(w + 2, *at<uint4>(row(s, vh, vec, 2), off));
+        }
+    }
+
     __device__ static __forceinline__ void unpack2(cx<real> *v, uint2 c, float sc)
     {
         v[0] = mk(sc * half_to_f<P>(c.x & 0xffff), sc * half_to_f<P>(c.x >> 16));
@@ -317,6 +382,21 @@ __host__ __device__ inline size_t gauge_parity_bytes(int prec, int recon, long v
 {
     size_t b = link_elem_bytes(prec) * (recon == 12 ? 6 : (recon == 8 ? 4 : 9)) * 4 * (size_t)vh;
     return (b + 255) & ~(size_t)255;
+}
+
+// conj(p q - r s), each part one FMA chain of four terms.
+template <typename T>
+__device__ __forceinline__ cx<T> conj_cross(cx<T> p, cx<T> q, cx<T> r, cx<T> s)
+{
+    T re = p.re * q.re;
+    re = fma(-p.im, q.im, re);
+    re = fma(-r.re, s.re, re);
+    re = fma(r.im, s.im, re);
+    T im = r.re * s.im;
+    im = fma(r.im, s.re, im);
+    im = fma(-p.re, q.im, im);
+    im = fma(-p.im, q.re, im);
+    return mk(re, im);
 }
 
 // Link rows of one parity (all [mu][cb], 16-byte rows first):
@@ -450,9 +530,9 @@ struct LinkIO {
                 for (int b = 0; b < 3; b++) u[a][b] = e[3 * a + b];
             if constexpr (RECON == 12) {
                 // third row of an SU(3) matrix: conj(row0 x row1)
-                u[2][0] = conjg(cmul(u[0][1], u[1][2]) - cmul(u[0][2], u[1][1]));
-                u[2][1] = conjg(cmul(u[0][2], u[1][0]) - cmul(u[0][0], u[1][2]));
-                u[2][2] = conjg(cmul(u[0][0], u[1][1]) - cmul(u[0][1], u[1][0]));
+                u[2][0] = conj_cross(u[0][1], u[1][2], u[0][2], u[1][1]);
+                u[2][1] = conj_cross(u[0][2], u[1][0], u[0][0], u[1][2]);
+                u[2][2] = conj_cross(u[0][0], u[1][1], u[0][1], u[1][0]);
             } else {
 #pragma unroll
                 for (int b = 0; b < 3; b++) u[2][b] = e[6 + b];
