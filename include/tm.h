@@ -282,13 +282,15 @@ int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm
              tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev);
 
 /* Autotuner: 1 enables the timing-based choice of the hop launch per kernel
- * variant and shape -- block size, link-load policy, cap of resident waves
- * per SIMD, LDS staging (FP32 one flavour), then the four fastest of those in
- * each depth of the brick site order -- cached per context and persisted to
- * $TM_TUNE_CACHE if set; 0 disables (defaults are then used).
- * Read at context creation, for experiments: TM_HOP_BS, TM_LINK_NT,
- * TM_HOP_WCAP, TM_HOP_ZC, TM_HOP_LDS fix one of those choices, TM_XCD_REMAP=0
- * turns off the XCD-aware block order.                                        */
+ * variant and shape -- right-hand sides per thread (1, 2 or 4 where they
+ * divide every problem's count; one flavour, 12-real links), block size,
+ * link-load policy, cap of resident waves per SIMD, LDS staging (FP32 one
+ * flavour), then the four fastest of those in each depth of the brick site
+ * order -- cached per context and persisted to $TM_TUNE_CACHE if set;
+ * 0 disables (defaults are then used).
+ * Read at context creation, for experiments: TM_HOP_NR, TM_HOP_BS,
+ * TM_LINK_NT, TM_HOP_WCAP, TM_HOP_ZC, TM_HOP_LDS fix one of those choices,
+ * TM_XCD_REMAP=0 turns off the XCD-aware block order.                         */
 int tm_set_tuning(tm_ctx *ctx, int enable);
 
 #ifdef __cplusplus

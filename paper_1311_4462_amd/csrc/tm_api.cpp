@@ -39,6 +39,7 @@ struct tm_ctx {
     int force_zc = -1;                 // TM_HOP_ZC: fixed brick depth of the site order (0: lexicographic)
     int force_wcap = -1;               // TM_HOP_WCAP: fixed cap of resident waves per SIMD (0: none)
     int force_ldss = -1;               // TM_HOP_LDS: 1 / 0 forces the LDS-staged variant where it exists
+    int force_nr = 0;                  // TM_HOP_NR: 1, 2 or 4 rhs per thread where instantiated (0: default)
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
 };
@@ -219,12 +220,20 @@ struct HopCall {
     double *red_out;
 };
 
-// rhs per thread: 4 for one flavour, 12-real links, reduced precisions
-// (an FP64 site vector for 4 rhs alone needs 192 VGPRs)
-int choose_nr(int prec, int nf, int nrhs, int recon)
+#ifndef TM_FP64_NR
+#define TM_FP64_NR 2
+#endif
+constexpr int kFp64Nr = TM_FP64_NR;
+
+// rhs per thread (one flavour, 12-real links): 4 for the reduced precisions,
+// 2 for FP64 (an FP64 site vector for 4 rhs alone needs 192 VGPRs); force
+// (1, 2 or 4) overrides where that variant exists.
+int choose_nr(int prec, int nf, int nrhs, int recon, int force)
 {
-    if (prec != TM_FP64 && nf == 1 && recon == 12 && nrhs % 4 == 0) return 4;
-    return 1;
+    if (nf != 1 || recon != 12) return 1;
+    if (force == 1 || force == 2 || (force == 4 && prec != TM_FP64)) return nrhs % force ? 1 : force;
+    const int want = (prec == TM_FP64) ? kFp64Nr : 4;
+    return nrhs % want ? 1 : want;
 }
 
 // Launch configurations instantiated for a hop variant (see TM_HOP_DEFINE):
@@ -240,7 +249,21 @@ struct HopCfg {
     int wcap;
     int zc = 0;     // z-planes per brick of the site order (0: lexicographic)
     bool ldss = false;   // x / y neighbours staged in LDS (FP32, one flavour, one rhs)
+    int nr = 1;     // right-hand sides per thread
 };
+// cache code of a tuned configuration
+int cfg_code(const HopCfg &c)
+{
+    const int l2nr = c.nr == 4 ? 2 : c.nr == 2 ? 1 : 0;
+    return c.bs | (c.lnt ? 1 << 16 : 0) | (c.ldss ? 1 << 17 : 0) | (l2nr << 18) | (c.wcap << 20) | (c.zc << 24);
+}
+HopCfg cfg_decode(int code)
+{
+    HopCfg c{code & 0xffff, ((code >> 16) & 1) != 0, (code >> 20) & 0xf, (code >> 24) & 0x7f,
+             ((code >> 17) & 1) != 0};
+    c.nr = 1 << ((code >> 18) & 3);
+    return c;
+}
 // bricks of at most `target` z-planes: the largest divisor of Lz below Lz
 int zc_for(int target, int Lz)
 {
@@ -444,11 +467,24 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         }
         return launch_hops(ctx, pre, n);
     }
-    int nr = 1 << 30;
-    for (int i = 0; i < n; i++) nr = std::min(nr, choose_nr(prec, nf, calls[i].nrhs, recon));
-    for (int i = 0; i < n; i++)
-        if (calls[i].nrhs % nr || clv) nr = 1;
-    const std::vector<HopCfg> cand = cfg_candidates(prec, nf, nr, twl, recon, clv);
+    // rhs per thread: the instantiated groupings that divide every problem's
+    // rhs count are tuning candidates; the heuristic choice is the default
+    std::vector<int> nrs;
+    for (int q : {1, 2, 4}) {
+        bool ok = q == 1 || (nf == 1 && recon == 12 && !clv && !(q == 4 && prec == TM_FP64));
+        for (int i = 0; i < n && ok; i++) ok = calls[i].nrhs % q == 0;
+        if (ok) nrs.push_back(q);
+    }
+    if (ctx->force_nr && std::find(nrs.begin(), nrs.end(), ctx->force_nr) != nrs.end()) nrs = {ctx->force_nr};
+    int nr_def = 1 << 30;
+    for (int i = 0; i < n; i++) nr_def = std::min(nr_def, choose_nr(prec, nf, calls[i].nrhs, recon, ctx->force_nr));
+    if (clv || std::find(nrs.begin(), nrs.end(), nr_def) == nrs.end()) nr_def = 1;
+    std::vector<HopCfg> cand;
+    for (int q : nrs)
+        for (HopCfg c : cfg_candidates(prec, nf, q, twl, recon, clv)) {
+            c.nr = q;
+            cand.push_back(c);
+        }
     long vh_total = 0;
     size_t wset = 0;
     for (int i = 0; i < n; i++) {
@@ -457,36 +493,37 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         wset += 2 * gauge_parity_bytes(prec, recon, g->vh) + 3 * spinor_field_bytes(prec, g->vh, nf, calls[i].nrhs);
     }
     HopCfg cfg = default_cfg(twl, wset);
-    const std::string key = tune_key(prec, nf, nr, dagger, twl, calls[0].epi, recon, vh_total, clv);
+    cfg.nr = nr_def;
+    const std::string key = tune_key(prec, nf, nrs.back(), dagger, twl, calls[0].epi, recon, vh_total, clv);
     auto it = ctx->tuned.find(key);
     if (ctx->force_bs || ctx->force_lnt >= 0) {
         HopCfg want{ctx->force_bs ? ctx->force_bs : cfg.bs, ctx->force_lnt >= 0 ? ctx->force_lnt != 0 : cfg.lnt,
                     0};
+        want.nr = nr_def;
         for (const HopCfg &c : cand)
-            if (c.bs == want.bs && c.lnt == want.lnt && c.wcap == 0) cfg = want;
+            if (c.bs == want.bs && c.lnt == want.lnt && c.wcap == 0 && c.nr == want.nr) cfg = want;
     } else if (it != ctx->tuned.end()) {
-        const int code = it->second;
-        cfg = HopCfg{code & 0xffff, ((code >> 16) & 1) != 0, (code >> 20) & 0xf, (code >> 24) & 0x7f,
-                     ((code >> 17) & 1) != 0};
+        cfg = cfg_decode(it->second);
     } else if (ctx->tuning && cand.size() > 1) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(ctx->stream, &cs);
         if (cs == hipStreamCaptureStatusNone) {
             // time the instantiated configurations on the real launch (hop
-            // launches are idempotent: out never aliases an input): block size
-            // x link-load policy x wave cap in lexicographic site order, then
-            // the four best of those with each brick depth of the site order
+            // launches are idempotent: out never aliases an input): rhs per
+            // thread x block size x link-load policy x wave cap in
+            // lexicographic site order, then the four best of those with each
+            // brick depth of the site order
             hipEvent_t e0, e1;
             TM_HIP(ctx, hipEventCreate(&e0));
             TM_HIP(ctx, hipEventCreate(&e1));
             // each trial: one untimed launch, then `reps` timed back to back
             auto trial = [&](const HopCfg &c, int reps, float *ms_per) -> int {
                 HopBatch B;
-                TM_TRY(build_hop_batch(ctx, calls, n, nr, c.bs, &B, c.zc));
-                TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, ctx->stream));
+                TM_TRY(build_hop_batch(ctx, calls, n, c.nr, c.bs, &B, c.zc));
+                TM_HIP(ctx, dispatch_hop(B, prec, nf, c.nr, dagger, twl, recon, c, clv, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
                 for (int r = 0; r < reps; r++)
-                    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, ctx->stream));
+                    TM_HIP(ctx, dispatch_hop(B, prec, nf, c.nr, dagger, twl, recon, c, clv, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e1, ctx->stream));
                 TM_HIP(ctx, hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -525,21 +562,20 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
                 }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            const int code = cfg.bs | (cfg.lnt ? 1 << 16 : 0) | (cfg.ldss ? 1 << 17 : 0) | (cfg.wcap << 20) |
-                             (cfg.zc << 24);
+            const int code = cfg_code(cfg);
             ctx->tuned[key] = code;
             save_tune(ctx, key, code);
         }
     }
     if (ctx->force_zc >= 0) cfg.zc = ctx->force_zc;
-    if (ctx->force_ldss >= 0 && (ctx->force_ldss == 0 || (prec == TM_FP32 && nf == 1 && nr == 1 &&
+    if (ctx->force_ldss >= 0 && (ctx->force_ldss == 0 || (prec == TM_FP32 && nf == 1 && cfg.nr == 1 &&
                                                             recon == 12 && !clv && !twl)))
         cfg.ldss = ctx->force_ldss != 0;
     if (cfg.ldss) cfg.zc = 0;
     if (ctx->force_wcap >= 0) cfg.wcap = ctx->force_wcap;
     HopBatch B;
-    TM_TRY(build_hop_batch(ctx, calls, n, nr, cfg.bs, &B, cfg.zc));
-    TM_HIP(ctx, dispatch_hop(B, prec, nf, nr, dagger, twl, recon, cfg, clv, ctx->stream));
+    TM_TRY(build_hop_batch(ctx, calls, n, cfg.nr, cfg.bs, &B, cfg.zc));
+    TM_HIP(ctx, dispatch_hop(B, prec, nf, cfg.nr, dagger, twl, recon, cfg, clv, ctx->stream));
     TM_TRY(finish_reductions(ctx, B.p, n));
     return TM_OK;
 }
@@ -722,6 +758,8 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (e) c->force_zc = std::max(0, atoi(e));
     e = getenv("TM_HOP_LDS");
     if (e) c->force_ldss = atoi(e) ? 1 : 0;
+    e = getenv("TM_HOP_NR");
+    if (e) c->force_nr = atoi(e);
     e = getenv("TM_HOP_WCAP");
     if (e) c->force_wcap = std::min(8, std::max(0, atoi(e)));
     e = getenv("TM_TUNE");

@@ -299,13 +299,16 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
     }
 }
 
-// One block per problem: add the partials in a fixed order, then finish.
+// One block per (problem, vector): add the vector's partials in a fixed
+// order, then finish.
 __global__ void __launch_bounds__(256) finish_kernel(const FinishBatch F)
 {
     __shared__ double sh[4];
     if (F.gate && *F.gate == 0) return;
     const Reduce &rd = F.r[blockIdx.x];
-    finish_reduce<256>(rd, rd.nvec, rd.nblk, sh);
+    const int v = (int)blockIdx.y;
+    if (v >= rd.nvec) return;
+    finish_reduce<256>(rd, v, v + 1, rd.nblk, sh);
 }
 
 __global__ void decide_kernel(const DecideArgs D)
@@ -329,7 +332,9 @@ hipError_t launch_decide(const DecideArgs &D, hipStream_t st)
 
 hipError_t launch_finish(const FinishBatch &F, hipStream_t st)
 {
-    hipLaunchKernelGGL(finish_kernel, dim3(F.nprob), dim3(256), 0, st, F);
+    int nv = 1;
+    for (int i = 0; i < F.nprob; i++) nv = std::max(nv, F.r[i].nvec);
+    hipLaunchKernelGGL(finish_kernel, dim3(F.nprob, nv), dim3(256), 0, st, F);
     return hipGetLastError();
 }
 

@@ -903,6 +903,9 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
             TM_HOP_CASES(P, 1, 4, 12, 128)                                                     \
             TM_HOP_CASES_TWL(P, 1, 4, 12)                                                      \
         }                                                                                      \
+        TM_HOP_CASES(P, 1, 2, 12, 256)                                                         \
+        TM_HOP_CASES(P, 1, 2, 12, 128)                                                         \
+        TM_HOP_CASES_TWL(P, 1, 2, 12)                                                          \
         TM_HOP_CASES_TWL(P, 1, 1, 12)                                                          \
         TM_HOP_CASES_TWL(P, 1, 1, 18)                                                          \
         TM_HOP_CASES_TWL(P, 2, 1, 12)                                                          \

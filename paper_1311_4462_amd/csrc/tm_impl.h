@@ -837,12 +837,12 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return s;
 }
 
-// Final reduction of partials[v][0..nblk) for v in [0, nvec) by one block,
+// Final reduction of partials[v][0..nblk) for v in [v0, v1) by one block,
 // then the finishing operation.  Fixed summation order.
 template <int BS>
-__device__ void finish_reduce(const Reduce &rd, int nvec, int nblk, double *sh)
+__device__ void finish_reduce(const Reduce &rd, int v0, int v1, int nblk, double *sh)
 {
-    for (int v = 0; v < nvec; v++) {
+    for (int v = v0; v < v1; v++) {
         double s = 0.0;
         for (int i = threadIdx.x; i < nblk; i += BS) s += rd.partials[(long)v * nblk + i];
         s = block_sum<BS>(s, sh);
