@@ -67,6 +67,29 @@ def time_launches(torch, fn, reps, warm=3):
     return e0.elapsed_time(e1) / reps * 1e-3   # seconds per launch
 
 
+def time_cold(torch, fn, reps, flush_bytes=512 << 20):
+    """Median per-call time with the caches flushed before each call: a read
+    of 512 MB (twice the last-level cache) on the same stream, outside the
+    timed interval, so the operator's fields come from HBM.  The flush only
+    reads, so it leaves no dirty lines whose write-back the timed call would
+    pay for."""
+    buf = torch.ones(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    fn()
+    for _ in range(3):
+        buf.sum()
+    for e0, e1 in evs:
+        buf.sum()
+        e0.record(s)
+        fn()
+        e1.record(s)
+    torch.cuda.synchronize()
+    ts = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    del buf
+    return ts[len(ts) // 2] * 1e-3
+
+
 def cpu_baseline(U, b_e, dims, vh, budget_s=15.0):
     """The FP64 oracle's asymmetric operator apply on this host (C loop + NumPy)."""
     from oracle import oracle as O
@@ -371,6 +394,10 @@ def main():
     flops = FLOPS_PER_SITE["deg_asym"] * vh
     value = flops / dt / 1e9
 
+    # the same apply with the caches flushed before each call (before the
+    # per-kernel timing, whose launches then end the trace of this section)
+    t_cold = time_cold(torch, step, 20)
+
     # per-kernel durations (HIP events on the stream the kernels run on)
     L, S = 48, 96
     b1, b2 = site_bytes(L, S)
@@ -390,12 +417,16 @@ def main():
     extra = {
         "hbm_gbs_mat_pc": round(mat_bytes / dt / 1e9, 1),
         "hbm_frac_mat_pc": round(mat_bytes / dt / 1e9 / PEAK_HBM_GBS, 4),
+        # the same apply with the caches flushed before each call
+        "mat_pc_fp32_cold": {"us": round(t_cold * 1e6, 2), "gbs": round(mat_bytes / t_cold / 1e9, 1),
+                             "frac": round(mat_bytes / t_cold / 1e9 / PEAK_HBM_GBS, 4)},
         "kernel_us": {"hop_twinv": round(t_k1 * 1e6, 2), "hop_rx_plus_kd": round(t_k2 * 1e6, 2)},
         "kernel_gbs": {"hop_twinv": round(b1 * vh / t_k1 / 1e9, 1),
                        "hop_rx_plus_kd": round(ach, 1)},
     }
     log(f"mat_pc fp32: {dt * 1e6:.1f} us/apply, {value:.1f} Gflop/s, "
-        f"{extra['hbm_gbs_mat_pc']} GB/s; kernels {extra['kernel_us']}")
+        f"{extra['hbm_gbs_mat_pc']} GB/s; kernels {extra['kernel_us']}; "
+        f"caches flushed: {extra['mat_pc_fp32_cold']}")
 
     # FP64 operator on the same lattice (context figure)
     x64 = api.tm_spinor_pack(ctx, b[None], p, api.FP64, 0)

@@ -180,3 +180,35 @@ def test_lds_staged_neighbours(api, monkeypatch):
         assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
         g.close()
     c.close()
+
+
+@pytest.mark.parametrize("nr", [1, 2, 4])
+def test_rhs_per_thread(api, nr, monkeypatch):
+    """Each grouping of right-hand sides per thread (1, 2 or 4; FP64 at most
+    2) gives the operator of the oracle on every rhs, and a batched mixed
+    solve reaches the FP64 tolerance."""
+    monkeypatch.setenv("TM_HOP_NR", str(nr))
+    c = api.Context()
+    dims = (6, 4, 8, 6)
+    p = api.make_params(dims, 0.16, 0.12, 0.0, 1)
+    op = oparams(p)
+    U = inputs.gauge_field(dims, "haar", 97)
+    g = api.Gauge(c, U, p, precs=(0, 1, 2, 3))
+    a = O.project(inputs.gaussian_spinor(dims, 1, 98, nrhs=4), dims, 0)
+    for prec in (0, 1, 2, 3):
+        t = to_native(api, c, a, p, prec, 0, 4)
+        aq = from_native(api, c, t, p, prec, 0, 4)
+        out = api.new_field(p, prec, 4)
+        for pc in (0, 1):
+            for dag in (0, 1):
+                api.tm_mat_pc(c, out, t, g, prec, pc, dag, nrhs=4)
+                got = from_native(api, c, out, p, prec, 0, 4)
+                for r in range(4):
+                    ref = O.mat_pc(op, U, aq[r], "asym" if pc == 0 else "sym", bool(dag))
+                    assert rel(got[r], ref) < TOL[prec], (prec, pc, dag, r)
+    tb = to_native(api, c, a, p, 0, 0, 4)
+    x = api.new_field(p, 0, 4)
+    res = api.tm_cg(c, x, tb, g, tol=1e-10, inner=2, nrhs=4)
+    assert all(r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10 for r in res)
+    g.close()
+    c.close()
