@@ -108,98 +108,6 @@ __device__ __forceinline__ void project(cx<T> (&h)[2][3], const cx<T> *v)
     }
 }
 
-// a + s b of two binary16 values, each the low (L = 0) or high (L = 1) half
-// of a 32-bit word, in one FP32 fused multiply-add with binary16 sources
-// (exact products, one rounding: the FP32 sum of the converted values).
-template <int LA, int LB, bool NEG>
-__device__ __forceinline__ float mix_add(uint32_t a, uint32_t b)
-{
-    float d;
-#define TM_MIX(SA, SB, N)                                                                              \
-    __asm__("v_fma_mix_f32 %0, %1, 1.0, " N "%2 op_sel:[" #SA ",0," #SB "] op_sel_hi:[1,0,1]" \
-            : "=v"(d)                                                                              \
-            : "v"(a), "v"(b))
-    if constexpr (!NEG) {
-        if constexpr (LA == 0 && LB == 0) TM_MIX(0, 0, "");
-        else if constexpr (LA == 0 && LB == 1) TM_MIX(0, 1, "");
-        else if constexpr (LA == 1 && LB == 0) TM_MIX(1, 0, "");
-        else TM_MIX(1, 1, "");
-    } else {
-        if constexpr (LA == 0 && LB == 0) TM_MIX(0, 0, "-");
-        else if constexpr (LA == 0 && LB == 1) TM_MIX(0, 1, "-");
-        else if constexpr (LA == 1 && LB == 0) TM_MIX(1, 0, "-");
-        else TM_MIX(1, 1, "-");
-    }
-#undef TM_MIX
-    return d;
-}
-
-// Complex a + k b of two binary16 complex words (real part low, imaginary
-// high) with k = +1 (K = 0), -1 (K = 1), +i (K = 2) or -i (K = 3).
-template <int K>
-__device__ __forceinline__ cx<float> mix_cadd(uint32_t a, uint32_t b)
-{
-    if constexpr (K == 0) return mk(mix_add<0, 0, false>(a, b), mix_add<1, 1, false>(a, b));
-    else if constexpr (K == 1) return mk(mix_add<0, 0, true>(a, b), mix_add<1, 1, true>(a, b));
-    else if constexpr (K == 2) return mk(mix_add<0, 1, true>(a, b), mix_add<1, 0, false>(a, b));
-    else return mk(mix_add<0, 1, false>(a, b), mix_add<1, 0, true>(a, b));
-}
-
-// project() for a half-precision neighbour given as stored words (without
-// its site scale): binary16 through mix_cadd, bfloat16 converted first.
-template <int P, int MU, int SIG>
-__device__ __forceinline__ void project_words(cx<float> (&h)[2][3], const uint32_t *w)
-{
-    auto cadd = [](auto kk, uint32_t a, uint32_t b) {
-        constexpr int K = decltype(kk)::value;
-        if constexpr (P == TM_FP16) {
-            return mix_cadd<K>(a, b);
-        } else {
-            const cx<float> x = mk(b2f((uint16_t)(a & 0xffff)), b2f((uint16_t)(a >> 16)));
-            const cx<float> y = mk(b2f((uint16_t)(b & 0xffff)), b2f((uint16_t)(b >> 16)));
-            if constexpr (K == 0) return x + y;
-            else if constexpr (K == 1) return x - y;
-            else if constexpr (K == 2) return x + times_i(y);
-            else return x + times_mi(y);
-        }
-    };
-    using k0 = std::integral_constant<int, 0>;
-    using k1 = std::integral_constant<int, 1>;
-    using k2 = std::integral_constant<int, 2>;
-    using k3 = std::integral_constant<int, 3>;
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        if constexpr (MU == 0) {
-            if constexpr (SIG > 0) {
-                h[0][c] = cadd(k3{}, w[c], w[9 + c]);
-                h[1][c] = cadd(k3{}, w[3 + c], w[6 + c]);
-            } else {
-                h[0][c] = cadd(k2{}, w[c], w[9 + c]);
-                h[1][c] = cadd(k2{}, w[3 + c], w[6 + c]);
-            }
-        } else if constexpr (MU == 1) {
-            if constexpr (SIG > 0) {
-                h[0][c] = cadd(k1{}, w[c], w[9 + c]);
-                h[1][c] = cadd(k0{}, w[3 + c], w[6 + c]);
-            } else {
-                h[0][c] = cadd(k0{}, w[c], w[9 + c]);
-                h[1][c] = cadd(k1{}, w[3 + c], w[6 + c]);
-            }
-        } else if constexpr (MU == 2) {
-            if constexpr (SIG > 0) {
-                h[0][c] = cadd(k3{}, w[c], w[6 + c]);
-                h[1][c] = cadd(k2{}, w[3 + c], w[9 + c]);
-            } else {
-                h[0][c] = cadd(k2{}, w[c], w[6 + c]);
-                h[1][c] = cadd(k3{}, w[3 + c], w[9 + c]);
-            }
-        } else {
-            h[0][c] = mk(half_to_f<P>((uint16_t)(w[c] & 0xffff)), half_to_f<P>((uint16_t)(w[c] >> 16)));
-            h[1][c] = mk(half_to_f<P>((uint16_t)(w[3 + c] & 0xffff)), half_to_f<P>((uint16_t)(w[3 + c] >> 16)));
-        }
-    }
-}
-
 // Rebuild the lower spin pair from the six link products g[s][c] (s: row of
 // the half spinor, c: colour) and accumulate with the factor sgn (boundary
 // sign, and 2 for the time projector) through the accumulating FMAs.
@@ -373,8 +281,9 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
 }
 
 // Load the neighbour vector vec at site nb for a hop in direction MU and
-// accumulate it (the half-precision site scale enters with the hop's factor;
-// half-precision values are converted inside the projection's additions).
+// accumulate it.  The half-precision site scale enters with the hop's factor;
+// binary16 neighbours go through the packed pairs above, the other formats
+// through project() and the FMA chains.
 template <int P, int MU, int SIG, bool BWD>
 __device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
                                          const cx<typename Prec<P>::real> (&u)[3][3], const SpinorPtr &in,
@@ -382,8 +291,7 @@ __device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
 {
     using real = typename Prec<P>::real;
     real sc;
-    cx<real> h[2][3];
-    if constexpr (P == TM_FP16 || P == TM_BF16) {
+    if constexpr (P == TM_FP16) {
         uint32_t w[12];
         if constexpr (MU == 3) {
             if constexpr (SIG > 0)
@@ -393,25 +301,21 @@ __device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
         } else {
             SpinorIO<P>::template load_words<0, 12>(w, in, vh, vec, nb, sc);
         }
-        if constexpr (P == TM_FP16 && kF16Pairs) {
-            f16x2 hp[2][3], hs[2][3], u2[3][3];
-            project_pairs<MU, SIG, BWD>(hp, hs, w);
+        f16x2 hp[2][3], hs[2][3], u2[3][3];
+        project_pairs<MU, SIG, BWD>(hp, hs, w);
 #pragma unroll
-            for (int a = 0; a < 3; a++)
+        for (int a = 0; a < 3; a++)
 #pragma unroll
-                for (int b = 0; b < 3; b++) u2[a][b] = (f16x2){(_Float16)u[a][b].re, (_Float16)u[a][b].im};
-            cx<float> g[2][3];
+            for (int b = 0; b < 3; b++) u2[a][b] = (f16x2){(_Float16)u[a][b].re, (_Float16)u[a][b].im};
+        cx<float> g[2][3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                g[0][c] = link_row_pairs<BWD>(u2, hp[0], hs[0], c);
-                g[1][c] = link_row_pairs<BWD>(u2, hp[1], hs[1], c);
-            }
-            accumulate_hop<MU, SIG>(acc, g, sgn * sc);
-            return;
+        for (int c = 0; c < 3; c++) {
+            g[0][c] = link_row_pairs<BWD>(u2, hp[0], hs[0], c);
+            g[1][c] = link_row_pairs<BWD>(u2, hp[1], hs[1], c);
         }
-        project_words<P, MU, SIG>(h, w);
+        accumulate_hop<MU, SIG>(acc, g, sgn * sc);
     } else {
-        cx<real> v[12];
+        cx<real> v[12], h[2][3];
         if constexpr (MU == 3) {
             if constexpr (SIG > 0)
                 SpinorIO<P>::template load_unscaled<6, 6>(v, in, vh, vec, nb, sc);
@@ -421,8 +325,8 @@ __device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
             SpinorIO<P>::template load_unscaled<0, 12>(v, in, vh, vec, nb, sc);
         }
         project<MU, SIG>(h, v);
+        mul_accumulate<MU, SIG, BWD>(acc, u, h, sgn * sc);
     }
-    mul_accumulate<MU, SIG, BWD>(acc, u, h, sgn * sc);
 }
 
 // Doublet sites are split over lane pairs: lane 2k holds flavour 0 and lane

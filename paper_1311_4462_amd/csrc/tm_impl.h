@@ -19,12 +19,6 @@ constexpr int kMaxProblems = 8;   // problems per batched launch
 #define TM_ND_SPLIT 0
 #endif
 constexpr bool kNdSplit = TM_ND_SPLIT != 0;
-// Binary16 hops: projection and link products on packed binary16 pairs with
-// two-term dot products (TM_F16_PAIRS=0: FP32 arithmetic after conversion).
-#ifndef TM_F16_PAIRS
-#define TM_F16_PAIRS 1
-#endif
-constexpr bool kF16Pairs = TM_F16_PAIRS != 0;
 constexpr int kBlock = 256;       // default threads per block
 
 // ------------------------------------------------------------------ complex
