@@ -352,8 +352,8 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the lattice would be split in t with halo exchange; see the design notes).",
+        print("bench.py measures one GPU only: there is no multi-GPU path (one would split "
+              "the lattice in t and exchange the spin-projected faces between neighbours).",
               file=sys.stderr)
         sys.exit(2)
 
