@@ -192,7 +192,7 @@ int tm_spinor_pack(tm_ctx *ctx, void *dst_native, const void *src_canonical,
 int tm_spinor_unpack(tm_ctx *ctx, void *dst_canonical, const void *src_native,
                      const tm_params *p, tm_prec prec, int parity, int nrhs, int basis);
 
-/* Fused hop (Sec. 2.1, "fused kernels"): out (parity out_parity) = epilogue of
+/* Fused hop (Sec. 2.1: the hop fused with its local epilogue): out (parity out_parity) = epilogue of
  * D in or D^+ in (in has the other parity).  twist_on_load = 1 applies R^-1
  * (R^-+ if dagger) to every neighbour before the hop, i.e. A = D R^-1 in.
  * x may be NULL for TM_EPI_NONE / TM_EPI_TWINV.  All fields share prec.       */
