@@ -272,11 +272,22 @@ int zc_for(int target, int Lz)
     return 0;
 }
 constexpr unsigned kLdsPerCU = 160u << 10;
+// Dynamic LDS of one block may not exceed what a compute unit has minus the
+// kernel's own static LDS (the reduction scratch, a few dozen bytes): a
+// larger request is an invalid dispatch.
+constexpr unsigned kLdsStaticReserve = 1u << 10;
+constexpr unsigned kLdsDynamicMax = kLdsPerCU - kLdsStaticReserve;
 unsigned hop_lds_bytes(const HopCfg &c)
 {
     if (c.wcap <= 0) return 0;
     const unsigned blocks = std::max(1u, (unsigned)(4 * c.wcap * 64 / c.bs));   // per compute unit
-    return ((kLdsPerCU / blocks) + 511u) & ~511u;
+    return std::min(((kLdsPerCU / blocks) + 511u) & ~511u, kLdsDynamicMax & ~511u);
+}
+// LDS of the staged x / y neighbours: six FP32 chunk rows of the block's
+// sites and one y-row either side
+unsigned hop_staging_bytes(int bs, int row)
+{
+    return (unsigned)(6 * (bs + 2 * row) * 16);
 }
 std::vector<HopCfg> cfg_candidates(int prec, int nf, int nr, int twl, int recon, bool clv)
 {
@@ -346,11 +357,11 @@ hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger,
 {
     unsigned lds = hop_lds_bytes(c);
     if (c.ldss) {
-        // six FP32 chunk rows of the block's sites and one y-row either side
         int row = 0;
         for (int i = 0; i < B.nprob; i++) row = std::max(row, B.p[i].X[0] / 2);
-        lds = std::max(lds, (unsigned)(6 * (c.bs + 2 * row) * 16));
+        lds = std::max(lds, hop_staging_bytes(c.bs, row));
     }
+    if (lds > kLdsDynamicMax) return hipErrorInvalidValue;   // never dispatched
     switch (prec) {
     case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
     case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
@@ -479,10 +490,15 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     int nr_def = 1 << 30;
     for (int i = 0; i < n; i++) nr_def = std::min(nr_def, choose_nr(prec, nf, calls[i].nrhs, recon, ctx->force_nr));
     if (clv || std::find(nrs.begin(), nrs.end(), nr_def) == nrs.end()) nr_def = 1;
+    // LDS staging only where the block's rows fit in half a compute unit's LDS
+    int xrow = 0;
+    for (int i = 0; i < n; i++) xrow = std::max(xrow, calls[i].g->p.dims[0] / 2);
+    auto staging_fits = [&](int bs) { return hop_staging_bytes(bs, xrow) <= kLdsPerCU / 2; };
     std::vector<HopCfg> cand;
     for (int q : nrs)
         for (HopCfg c : cfg_candidates(prec, nf, q, twl, recon, clv)) {
             c.nr = q;
+            if (c.ldss && !staging_fits(c.bs)) continue;
             cand.push_back(c);
         }
     long vh_total = 0;
@@ -569,7 +585,8 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     }
     if (ctx->force_zc >= 0) cfg.zc = ctx->force_zc;
     if (ctx->force_ldss >= 0 && (ctx->force_ldss == 0 || (prec == TM_FP32 && nf == 1 && cfg.nr == 1 &&
-                                                            recon == 12 && !clv && !twl)))
+                                                            recon == 12 && !clv && !twl &&
+                                                            staging_fits(cfg.bs))))
         cfg.ldss = ctx->force_ldss != 0;
     if (cfg.ldss) cfg.zc = 0;
     if (ctx->force_wcap >= 0) cfg.wcap = ctx->force_wcap;

@@ -212,3 +212,30 @@ def test_rhs_per_thread(api, nr, monkeypatch):
     assert all(r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10 for r in res)
     g.close()
     c.close()
+
+
+def test_wave_cap_one_block_per_cu(api, monkeypatch):
+    """A wave cap of one per SIMD with 256-thread blocks asks for a whole
+    compute unit's LDS per block; the reservation leaves room for the
+    kernel's own LDS, so every hop (twist-on-load included) still runs and
+    matches the oracle."""
+    monkeypatch.setenv("TM_HOP_WCAP", "1")
+    monkeypatch.setenv("TM_HOP_BS", "256")
+    c = api.Context()
+    dims = (6, 4, 8, 6)
+    for flavor in (1, 2):
+        p = api.make_params(dims, 0.16, 0.12, 0.17 if flavor == 2 else 0.0, flavor)
+        op = oparams(p)
+        U = inputs.gauge_field(dims, "haar", 99)
+        g = api.Gauge(c, U, p, precs=(0, 1))
+        x = O.project(inputs.gaussian_spinor(dims, op.nf, 100), dims, 0)
+        for prec in (0, 1):
+            t = to_native(api, c, x, p, prec, 0)
+            out = api.new_field(p, prec)
+            for pc in (0, 1):
+                for dag in (0, 1):
+                    api.tm_mat_pc(c, out, t, g, prec, pc, dag)
+                    ref = O.mat_pc(op, U, x, "asym" if pc == 0 else "sym", bool(dag))
+                    assert rel(from_native(api, c, out, p, prec, 0)[0], ref) < TOL[prec]
+        g.close()
+    c.close()
