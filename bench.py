@@ -3,16 +3,25 @@
 FP64 CG time to a 1e-10 residual.
 
 Timed step = one application of the asymmetric even-odd preconditioned operator
-(Eq. 2.2, the operator Table 1 of the paper measures): two fused hop kernels,
-FP32 storage and arithmetic, 12-real links, degenerate flavour, 24^3 x 48
-lattice (kappa = 0.1615, mu = 0.004, near-unit SU(3) links), inputs resident in
-HBM.  Flops per even site: 2808 (1320 per hop, twist and xpay as counted in
-the design notes); algorithmic bytes per even site: 16 L + 5 S.
+of the non-degenerate doublet (Eq. 2.2 with the flavour-mixing twist of
+Eq. 2.1; the operator and lattice of the paper's Table 1, non-degenerate
+row): two fused hop kernels, FP32 storage and arithmetic, 12-real links,
+32^3 x 64 lattice, kappa = 0.1615, mu = 0.15, epsilon = 0.19, near-unit SU(3)
+links, inputs resident in HBM.  Flops per even site: 5808 (1320 per hop and
+flavour, twist and xpay as counted in the design notes); algorithmic bytes per
+even site: 16 L + 5 S (L = 48 B per stored link, S = 192 B per doublet site).
+The working set (403 MB of links, three 201 MB spinor fields) is well above
+the 256 MB last-level cache.
 
-Also reported (not timed in the K steps): per-kernel durations from HIP events
-with the roofline of the dominant kernel, the FP64 CPU oracle on the host as a
-baseline, and the 32^3 x 64 non-degenerate doublet CG comparison (FP64 CG vs
-mixed precision with FP64 reliable updates) to a 1e-10 true residual.
+The per-kernel durations of the roofline come from HIP events recorded on the
+library's stream between the two kernels of every timed step.
+
+Also reported: the same operator in FP64 / FP16 / BF16 and for one flavour,
+the 24^3 x 48 degenerate operator (warm and with the caches flushed), the FP64
+CPU oracle on the host (one thread and all threads, at 24^3 x 48 and at
+32^3 x 64, and a full FP64 CG on the 4^4 lattice), the 32^3 x 64 doublet CG
+comparison (FP64 CG vs mixed precision with FP64 reliable updates) to a 1e-10
+true residual, batched sources, uneven lattices and the force kernel.
 """
 import argparse
 import json
@@ -27,10 +36,23 @@ sys.path.insert(0, ROOT)
 METRIC = "tm Dslash Gflop/s + HBM GB/s; mixed vs FP64 CG time to 1e-10 residual"
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_SITE = {"deg_asym": 2808, "deg_sym": 2832, "nd": 5808}
+BYTES_PER_REAL = {0: 8, 1: 4, 2: 2, 3: 2}     # FP64, FP32, FP16, BF16
+HEADLINE_DIMS = (32, 32, 32, 64)
+HEADLINE = dict(kappa=0.1615, mu=0.15, eps=0.19)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic.json")
+HOP_SOURCES = ("tm_hop.inc.h", "tm_impl.h", "tm_hop_fp32.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def link_bytes(prec, recon=12):
+    return recon * BYTES_PER_REAL[prec]
+
+
+def site_spinor_bytes(prec, nf):
+    return (24 * BYTES_PER_REAL[prec] if prec in (0, 1) else 52) * nf
 
 
 def site_bytes(L, S):
@@ -38,16 +60,20 @@ def site_bytes(L, S):
     return 8 * L + 2 * S, 8 * L + 3 * S
 
 
-def measured_traffic():
-    """HBM-side bytes per launch of the roofline kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source changed since."""
+def hop_source_hash():
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1311_4462_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in HOP_SOURCES)
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM-side bytes per launch of the roofline kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary (two rocprofv3 --pmc runs of this bench),
+    or None if the kernel source or the workload changed since."""
     try:
-        t = json.load(open(os.path.join(ROOT, "profiles", "hop_traffic.json")))
-        csrc = os.path.join(ROOT, "paper_1311_4462_amd", "csrc")
-        src = b"".join(open(os.path.join(csrc, f), "rb").read()
-                       for f in ("tm_hop.inc.h", "tm_impl.h", "tm_hop_fp32.hip"))
-        if hashlib.sha256(src).hexdigest()[:16] != t["source_sha256_16"]:
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("workload") != workload or hop_source_hash() != t["source_sha256_16"]:
             return None
         return int(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -55,7 +81,7 @@ def measured_traffic():
 
 
 def time_launches(torch, fn, reps, warm=3):
-    for _ in range(warm):          # first calls may run the block-size tuner
+    for _ in range(warm):          # first calls may run the tuner
         fn()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -90,45 +116,102 @@ def time_cold(torch, fn, reps, flush_bytes=512 << 20):
     return ts[len(ts) // 2] * 1e-3
 
 
-def cpu_baseline(U, b_e, dims, vh, budget_s=15.0):
-    """The FP64 oracle's asymmetric operator apply on this host (C loop + NumPy)."""
-    from oracle import oracle as O
-    op = O.Params(dims, 0.1615, 0.004, 0.0, O.PLUS)
+def kernel_split(torch, api, ctx, g, p, prec, x, tmp, y, reps):
+    """The asymmetric operator as its two ABI hop calls, with HIP events on the
+    library's stream around each kernel: returns (K1 s, K2 s, step s)."""
+    s = torch.cuda.current_stream()
+    k2 = -p.kappa ** 2
+
+    def k1_call():
+        api.tm_dslash(ctx, tmp, x, g, prec, 1, 0, 0, api.EPI_TWINV, None, 0.0)
+
+    def k2_call():
+        api.tm_dslash(ctx, y, tmp, g, prec, 0, 0, 0, api.EPI_RX_PLUS_KD, x, k2)
+
+    for _ in range(3):
+        k1_call()
+        k2_call()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    for r in range(reps):
+        k1_call()
+        ev[2 * r + 1].record(s)
+        k2_call()
+        ev[2 * r + 2].record(s)
+    ev[-1].synchronize()
+    t1 = [ev[2 * r].elapsed_time(ev[2 * r + 1]) * 1e-3 for r in range(reps)]
+    t2 = [ev[2 * r + 1].elapsed_time(ev[2 * r + 2]) * 1e-3 for r in range(reps)]
+    return sum(t1) / reps, sum(t2) / reps, ev[0].elapsed_time(ev[-1]) * 1e-3 / reps
+
+
+def headline(torch, api, ctx, g, p, a):
+    """Timed region: K steps of the FP32 doublet operator, each its two hop
+    kernels with events between them, after W untimed steps."""
+    import numpy as np
+    nf = 2
+    vh = int(np.prod(HEADLINE_DIMS)) // 2
+    prec = api.FP32
+    from paper_1311_4462_amd import inputs
+    src = torch.from_numpy(inputs.gaussian_spinor(HEADLINE_DIMS, nf, 2003)).cuda()
+    x = api.tm_spinor_pack(ctx, src[None], p, prec, 0)
+    del src
+    y = api.new_field(p, prec)
+    tmp = api.new_field(p, prec)
+    k2c = -p.kappa ** 2
+    s = torch.cuda.current_stream()
+
+    def step():
+        api.tm_dslash(ctx, tmp, x, g, prec, 1, 0, 0, api.EPI_TWINV, None, 0.0)
+        api.tm_dslash(ctx, y, tmp, g, prec, 0, 0, 0, api.EPI_RX_PLUS_KD, x, k2c)
+
+    for _ in range(a.warmup):
+        step()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * a.steps + 1)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    O.mat_pc(op, U, b_e, "asym")
-    t1 = time.perf_counter() - t0
-    n = max(1, min(8, int(budget_s / max(t1, 1e-3))))
-    ts = [t1]
-    for _ in range(n - 1):
-        t0 = time.perf_counter()
-        O.mat_pc(op, U, b_e, "asym")
-        ts.append(time.perf_counter() - t0)
-    t = statistics.median(ts)
-    return {"value": round(FLOPS_PER_SITE["deg_asym"] * vh / t / 1e9, 3), "unit": "Gflop/s",
-            "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{len(ts)} FP64 applies of the asymmetric preconditioned operator at "
-                      f"{'x'.join(map(str, dims))} (median {t:.2f} s each)"}
+    ev[0].record(s)
+    for r in range(a.steps):
+        api.tm_dslash(ctx, tmp, x, g, prec, 1, 0, 0, api.EPI_TWINV, None, 0.0)
+        ev[2 * r + 1].record(s)
+        api.tm_dslash(ctx, y, tmp, g, prec, 0, 0, 0, api.EPI_RX_PLUS_KD, x, k2c)
+        ev[2 * r + 2].record(s)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    t_k1 = sum(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(a.steps)) * 1e-3 / a.steps
+    t_k2 = sum(ev[2 * r + 1].elapsed_time(ev[2 * r + 2]) for r in range(a.steps)) * 1e-3 / a.steps
+    # the same operator through tm_mat_pc (one ABI call), and with the caches
+    # flushed before each apply
+    t_mat = time_launches(torch, lambda: api.tm_mat_pc(ctx, y, x, g, prec, api.ASYM, 0), a.kernel_reps)
+    t_cold = time_cold(torch, step, 20)
+    del x, y, tmp
+    L, S = link_bytes(prec), site_spinor_bytes(prec, nf)
+    b1, b2 = site_bytes(L, S)
+    return dict(dt=dt, t_k1=t_k1, t_k2=t_k2, t_mat=t_mat, t_cold=t_cold, b1=b1, b2=b2, vh=vh)
 
 
-BYTES_PER_REAL = {0: 8, 1: 4, 2: 2, 3: 2}     # FP64, FP32, FP16, BF16
-
-
-def mat_pc_rates(torch, api, ctx, g, p, precs, reps, flops_site, recon=12):
-    """Per-precision asymmetric M apply on a resident field: us, Gflop/s, algorithmic GB/s."""
+def kernel_rates(torch, api, ctx, g, p, precs, reps, flops_site, recon=12):
+    """Per precision: the asymmetric operator and its two kernels on a
+    resident field: us, Gflop/s, algorithmic GB/s and fraction of peak."""
     import numpy as np
     nf = 2 if p.flavor == api.NDEG else 1
     vh = int(np.prod(tuple(p.dims))) // 2
-    L = {q: recon * BYTES_PER_REAL[q] for q in (api.FP64, api.FP32, api.FP16, api.BF16)}
-    S = {api.FP64: 192 * nf, api.FP32: 96 * nf, api.FP16: 52 * nf, api.BF16: 52 * nf}
     src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
     out = {}
     for prec in precs:
         x = api.tm_spinor_pack(ctx, src, p, prec, 0)
         y = api.new_field(p, prec)
+        tmp = api.new_field(p, prec)
+        t1, t2, _ = kernel_split(torch, api, ctx, g, p, prec, x, tmp, y, reps)
         t = time_launches(torch, lambda: api.tm_mat_pc(ctx, y, x, g, prec, api.ASYM, 0), reps)
-        out[api.PREC_NAMES[prec]] = {"us": round(t * 1e6, 1), "gflops": round(flops_site * vh / t / 1e9, 1),
-                                     "gbs": round((16 * L[prec] + 5 * S[prec]) * vh / t / 1e9, 1)}
-        del x, y
+        b1, b2 = site_bytes(link_bytes(prec, recon), site_spinor_bytes(prec, nf))
+        out[api.PREC_NAMES[prec]] = {
+            "us": round(t * 1e6, 1), "gflops": round(flops_site * vh / t / 1e9, 1),
+            "gbs": round((b1 + b2) * vh / t / 1e9, 1),
+            "frac": round((b1 + b2) * vh / t / 1e9 / PEAK_HBM_GBS, 4),
+            "k1_us": round(t1 * 1e6, 1), "k1_frac": round(b1 * vh / t1 / 1e9 / PEAK_HBM_GBS, 4),
+            "k2_us": round(t2 * 1e6, 1), "k2_frac": round(b2 * vh / t2 / 1e9 / PEAK_HBM_GBS, 4)}
+        del x, y, tmp
     del src
     return out
 
@@ -140,8 +223,6 @@ def operator_variants(torch, api, ctx, U, p, reps):
     twisted-clover apply."""
     Ut = torch.from_numpy(U).cuda()
     out = {}
-    # one flavour twisted up (PLUS) with 18/12/8-real links, then twisted down
-    # (MINUS) and the doublet (eps = 0.19) with 12-real links
     cases = [(api.PLUS, r, "") for r in (18, 12, 8)] + [(api.MINUS, 12, "_minus"), (api.NDEG, 12, "_nd")]
     for flavor, recon, tag in cases:
         pf = api.make_params(tuple(p.dims), p.kappa, p.mu, 0.19 if flavor == api.NDEG else 0.0, flavor)
@@ -159,8 +240,6 @@ def operator_variants(torch, api, ctx, U, p, reps):
             del x, y
         g.close()
     src = torch.randn(api.canonical_shape(p), dtype=torch.complex128, device="cuda")
-    # twisted clover (c_sw = 1.57): the same asymmetric apply, with the clover
-    # blocks read by both kernels (A and B by the R^-1 kernel, A by the R kernel)
     import numpy as np
     vh = int(np.prod(tuple(p.dims))) // 2
     pc = api.make_params(tuple(p.dims), p.kappa, p.mu, 0.0, p.flavor, csw=1.57)
@@ -181,37 +260,104 @@ def operator_variants(torch, api, ctx, U, p, reps):
     return out
 
 
-def cg_comparison(torch, api, inputs, reps=3):
-    """32^3 x 64 doublet, mu = 0.15, eps = 0.19, kappa = 0.1615: FP64 CG vs mixed CG;
-    also the operator apply rates on this lattice (doublet in all precisions, one
-    flavour in FP32), whose working sets exceed the 256 MB last-level cache."""
-    dims = (32, 32, 32, 64)
-    p = api.make_params(dims, 0.1615, 0.15, 0.19, api.NDEG)
-    log("cg: generating 32^3x64 links")
-    U = inputs.gauge_field(dims, "near_unit", 1003)
-    Ut = torch.from_numpy(U).cuda()
-    del U
+def section_24(torch, api, inputs, a):
+    """24^3 x 48 degenerate FP32 / FP64 operator: warm (its ~223 MB FP32 working
+    set largely resident in the 256 MB last-level cache) and with the caches
+    flushed; the operator variants."""
+    import numpy as np
+    dims = (24, 24, 24, 48)
+    vh = int(np.prod(dims)) // 2
+    p = api.make_params(dims, 0.1615, 0.004, 0.0, api.PLUS)
+    log("bench: generating 24^3x48 links")
+    U = inputs.gauge_field(dims, "near_unit", 1002)
     ctx = api.Context()
     ctx.set_tuning(True)
-    g = api.Gauge(ctx, Ut, p, recon=12, precs=(api.FP64, api.FP32, api.FP16, api.BF16))
-    rates = {"nd": mat_pc_rates(torch, api, ctx, g, p, (api.FP64, api.FP32, api.FP16, api.BF16), 20,
-                                FLOPS_PER_SITE["nd"])}
-    pd = api.make_params(dims, 0.1615, 0.004, 0.0, api.PLUS)
-    gd = api.Gauge(ctx, Ut, pd, recon=12, precs=(api.FP32,))
-    rates["deg"] = mat_pc_rates(torch, api, ctx, gd, pd, (api.FP32,), 20, FLOPS_PER_SITE["deg_asym"])
-    gd.close()
-    # 8-real links: the same applies with a third fewer link bytes
-    g8 = api.Gauge(ctx, Ut, p, recon=8, precs=(api.FP32, api.FP16))
-    rates["nd_recon8"] = mat_pc_rates(torch, api, ctx, g8, p, (api.FP32, api.FP16), 20,
-                                      FLOPS_PER_SITE["nd"], recon=8)
-    g8.close()
-    gd8 = api.Gauge(ctx, Ut, pd, recon=8, precs=(api.FP32,))
-    rates["deg_recon8"] = mat_pc_rates(torch, api, ctx, gd8, pd, (api.FP32,), 20,
-                                       FLOPS_PER_SITE["deg_asym"], recon=8)
-    gd8.close()
-    log(f"32^3x64 mat_pc rates: {rates}")
-    del Ut
-    b = inputs.gaussian_spinor(dims, 2, 2003)
+    g = api.Gauge(ctx, torch.from_numpy(U).cuda(), p, recon=12, precs=(api.FP64, api.FP32))
+    b = inputs.gaussian_spinor(dims, 1, 2002)
+    out = {"rates": kernel_rates(torch, api, ctx, g, p, (api.FP32, api.FP64), a.kernel_reps,
+                                 FLOPS_PER_SITE["deg_asym"])}
+    x = api.tm_spinor_pack(ctx, b[None], p, api.FP32, 0)
+    y = api.new_field(p, api.FP32)
+    t_cold = time_cold(torch, lambda: api.tm_mat_pc(ctx, y, x, g, api.FP32, api.ASYM, 0), 20)
+    mb = (16 * 48 + 5 * 96) * vh
+    out["fp32_cold"] = {"us": round(t_cold * 1e6, 2), "gbs": round(mb / t_cold / 1e9, 1),
+                        "frac": round(mb / t_cold / 1e9 / PEAK_HBM_GBS, 4)}
+    del x, y
+    if not a.no_batch:
+        out["variants_us"] = operator_variants(torch, api, ctx, U, p, a.kernel_reps)
+    g.close()
+    ctx.close()
+    log(f"24^3x48: {out.get('rates')} cold {out['fp32_cold']}")
+    return out, U, b
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inputs, U3, U2, b2, with_c2_cg=False):
+    """The FP64 oracle on this host: the asymmetric operator at 24^3 x 48
+    (degenerate) and 32^3 x 64 (doublet) on one thread and on all threads,
+    and a full FP64 CG (tiny 4^4 lattice; 24^3 x 48 on request)."""
+    from oracle import oracle as O
+    runs = []
+    nthreads = O.num_threads()
+
+    def apply_runs(tag, op, U, b, flops, reps_all):
+        for th, reps in ((1, 1), (nthreads, reps_all)):
+            O.set_num_threads(th)
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                O.mat_pc(op, U, b, "asym")
+                ts.append(time.perf_counter() - t0)
+            t = statistics.median(ts)
+            runs.append({"run": tag, "threads": th, "applies": reps, "seconds": round(t, 3),
+                         "gflops": round(flops / t / 1e9, 3)})
+            log(f"cpu baseline {tag} threads={th}: {t:.2f} s")
+        O.set_num_threads(nthreads)
+
+    dims2 = (24, 24, 24, 48)
+    op2 = O.Params(dims2, 0.1615, 0.004, 0.0, O.PLUS)
+    b2e = O.project(b2, dims2, 0)
+    apply_runs("mat_pc_asym_24x24x24x48_deg", op2, U2, b2e, FLOPS_PER_SITE["deg_asym"] * 331776, 3)
+    op3 = O.Params(HEADLINE_DIMS, HEADLINE["kappa"], HEADLINE["mu"], HEADLINE["eps"], O.NDEG)
+    b3e = O.project(inputs.gaussian_spinor(HEADLINE_DIMS, 2, 2003), HEADLINE_DIMS, 0)
+    apply_runs("mat_pc_asym_32x32x32x64_nd", op3, U3, b3e, FLOPS_PER_SITE["nd"] * 1048576, 3)
+    del b3e
+    # full FP64 CG on the tiny lattice (Haar links, kappa = 0.160, mu = 0.01)
+    cgs = [((4, 4, 4, 4), "haar", 1001, 0.160, 0.01, "sym")]
+    if with_c2_cg:
+        cgs.append((dims2, None, None, 0.1615, 0.004, "asym"))
+    for dims, kind, seed, kappa, mu, pc in cgs:
+        op = O.Params(dims, kappa, mu, 0.0, O.PLUS)
+        U = U2 if kind is None else inputs.gauge_field(dims, kind, seed)
+        b = b2e if kind is None else O.project(inputs.gaussian_spinor(dims, 1, 2001), dims, 0)
+        t0 = time.perf_counter()
+        _, info = O.cg(op, U, b, pc, tol=1e-10)
+        t = time.perf_counter() - t0
+        runs.append({"run": f"cg_fp64_{'x'.join(map(str, dims))}_deg_{pc}", "threads": nthreads,
+                     "seconds": round(t, 3), "iters": info["iters"],
+                     "true_rel_res_normal": info["true_rel_res_normal"]})
+        log(f"cpu baseline cg {dims}: {t:.2f} s, {info['iters']} iterations")
+    head = [r for r in runs if r["run"] == "mat_pc_asym_32x32x32x64_nd" and r["threads"] == nthreads][0]
+    return {"value": head["gflops"], "unit": "Gflop/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"median of {head['applies']} FP64 oracle applies of the headline operator "
+                      f"(32^3x64 doublet, asymmetric) on {nthreads} threads, {head['seconds']} s each; "
+                      f"the other runs in 'runs'",
+            "runs": runs}
+
+
+def cg_comparison(torch, api, ctx, g, p, inputs, reps=3):
+    """32^3 x 64 doublet, mu = 0.15, eps = 0.19, kappa = 0.1615: FP64 CG vs mixed CG."""
+    b = inputs.gaussian_spinor(HEADLINE_DIMS, 2, 2003)
     tb = api.tm_spinor_pack(ctx, b[None], p, api.FP64, 0)
     del b
     out = {}
@@ -233,10 +379,7 @@ def cg_comparison(torch, api, inputs, reps=3):
                      "true_rel_res_normal": res["true_rel_res_normal"],
                      "true_rel_res_pc": res["true_rel_res_pc"], "status": res["status"]}
         log(f"cg {name}: {out[name]}")
-    g.close()
-    ctx.close()
     out["speedup_fp16_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed_fp16"]["seconds"], 3)
-    out["mat_pc_rates"] = rates
     return out
 
 
@@ -311,7 +454,7 @@ def batched_section(torch, api, inputs):
 
 
 def force_section(torch, api, inputs):
-    """16^3 x 32 doublet: FP32 force kernel time and bytes, and one autograd step
+    """16^3 x 32 doublet: FP32 force kernel time and one autograd step
     (FP64 solve recomputed in backward + force)."""
     from paper_1311_4462_amd.autograd import tm_action
     dims = (16, 16, 16, 32)
@@ -336,15 +479,23 @@ def force_section(torch, api, inputs):
                                       "links": 4 * 2 * vh}}
 
 
+WORKLOAD = ("tm_mat_pc asymmetric, non-degenerate doublet (mu 0.15, eps 0.19, kappa 0.1615), "
+            "32^3x64, FP32, 12-real links")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cg-24", action="store_true",
+                    help="also time a full FP64 oracle CG at 24^3x48 (about a minute of CPU)")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
-    ap.add_argument("--cg-only", action="store_true", help="only the CG comparison")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed 32^3x64 doublet section (for profiling it)")
+    ap.add_argument("--cg-only", action="store_true", help="only the 32^3x64 CG comparison")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the operator-variant, batched and force sections")
     ap.add_argument("--cg-reps", type=int, default=3)
@@ -357,130 +508,96 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1311_4462_amd import api, inputs
 
     torch.cuda.set_device(0)
-    if a.cg_only:
-        print(json.dumps({"cg_32x32x32x64_nd": cg_comparison(torch, api, inputs, a.cg_reps)}), flush=True)
-        return
-    dims = (24, 24, 24, 48)
-    vh = int(np.prod(dims)) // 2
-    p = api.make_params(dims, 0.1615, 0.004, 0.0, api.PLUS)
-    log("bench: generating 24^3x48 links")
-    U = inputs.gauge_field(dims, "near_unit", 1002)
+    p = api.make_params(HEADLINE_DIMS, HEADLINE["kappa"], HEADLINE["mu"], HEADLINE["eps"], api.NDEG)
+    log("bench: generating 32^3x64 links")
+    U3 = inputs.gauge_field(HEADLINE_DIMS, "near_unit", 1003)
     ctx = api.Context()
-    ctx.set_tuning(True)      # block size and link-load policy picked by timing, once per shape
-    g = api.Gauge(ctx, torch.from_numpy(U).cuda(), p, recon=12, precs=(api.FP64, api.FP32))
-    b = inputs.gaussian_spinor(dims, 1, 2002)
-    from oracle import oracle as O  # only for the even projection of the CPU-baseline input
-    b_e = O.project(b, dims, 0) if not a.no_cpu_baseline else None
-    x = api.tm_spinor_pack(ctx, b[None], p, api.FP32, 0)
-    y = api.new_field(p, api.FP32)
-
-    def step():
-        api.tm_mat_pc(ctx, y, x, g, api.FP32, api.ASYM, 0)
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / a.steps
-    flops = FLOPS_PER_SITE["deg_asym"] * vh
-    value = flops / dt / 1e9
-
-    # the same apply with the caches flushed before each call (before the
-    # per-kernel timing, whose launches then end the trace of this section)
-    t_cold = time_cold(torch, step, 20)
-
-    # per-kernel durations (HIP events on the stream the kernels run on)
-    L, S = 48, 96
-    b1, b2 = site_bytes(L, S)
-    tmp = api.new_field(p, api.FP32, 1)
-    kappa2 = -p.kappa ** 2
-    t_k1 = time_launches(torch, lambda: api.tm_dslash(ctx, tmp, x, g, api.FP32, 1, 0, 0,
-                                                      api.EPI_TWINV, None, 0.0), a.kernel_reps)
-    t_k2 = time_launches(torch, lambda: api.tm_dslash(ctx, y, tmp, g, api.FP32, 0, 0, 0,
-                                                      api.EPI_RX_PLUS_KD, x, kappa2), a.kernel_reps)
-    ach = b2 * vh / t_k2 / 1e9
-    mat_bytes = (b1 + b2) * vh
+    ctx.set_tuning(True)      # launch shapes picked by timing, once per kernel and shape
+    Ut = torch.from_numpy(U3).cuda()
+    precs = (api.FP32,) if a.headline_only else (api.FP64, api.FP32, api.FP16, api.BF16)
+    g = api.Gauge(ctx, Ut, p, recon=12, precs=precs)
+    h = headline(torch, api, ctx, g, p, a)
+    vh = h["vh"]
+    value = FLOPS_PER_SITE["nd"] * vh / h["dt"] / 1e9
+    ach = h["b2"] * vh / h["t_k2"] / 1e9
+    mat_bytes = (h["b1"] + h["b2"]) * vh
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(WORKLOAD),
                 "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "hop_kernel<FP32, 1 flavour, 1 rhs, 12-real links> with epilogue R x + k D",
-                "bytes_per_launch": b2 * vh, "us_per_launch": round(t_k2 * 1e6, 2)}
+                "kernel": "hop_kernel<FP32, doublet, 12-real links>, epilogue R x + k D (second "
+                          "kernel of the operator)",
+                "bytes_per_site": h["b2"], "sites_per_launch": vh,
+                "bytes_per_launch": h["b2"] * vh, "us_per_launch": round(h["t_k2"] * 1e6, 2)}
     extra = {
-        "hbm_gbs_mat_pc": round(mat_bytes / dt / 1e9, 1),
-        "hbm_frac_mat_pc": round(mat_bytes / dt / 1e9 / PEAK_HBM_GBS, 4),
-        # the same apply with the caches flushed before each call
-        "mat_pc_fp32_cold": {"us": round(t_cold * 1e6, 2), "gbs": round(mat_bytes / t_cold / 1e9, 1),
-                             "frac": round(mat_bytes / t_cold / 1e9 / PEAK_HBM_GBS, 4)},
-        "kernel_us": {"hop_twinv": round(t_k1 * 1e6, 2), "hop_rx_plus_kd": round(t_k2 * 1e6, 2)},
-        "kernel_gbs": {"hop_twinv": round(b1 * vh / t_k1 / 1e9, 1),
-                       "hop_rx_plus_kd": round(ach, 1)},
+        "operator": {"us": round(h["dt"] * 1e6, 2), "gbs": round(mat_bytes / h["dt"] / 1e9, 1),
+                     "frac": round(mat_bytes / h["dt"] / 1e9 / PEAK_HBM_GBS, 4),
+                     "us_one_call": round(h["t_mat"] * 1e6, 2)},
+        "operator_caches_flushed": {"us": round(h["t_cold"] * 1e6, 2),
+                                    "frac": round(mat_bytes / h["t_cold"] / 1e9 / PEAK_HBM_GBS, 4)},
+        "kernels": {"k1_twinv": {"us": round(h["t_k1"] * 1e6, 2), "bytes_per_site": h["b1"],
+                                 "frac": round(h["b1"] * vh / h["t_k1"] / 1e9 / PEAK_HBM_GBS, 4)},
+                    "k2_rx_plus_kd": {"us": round(h["t_k2"] * 1e6, 2), "bytes_per_site": h["b2"],
+                                      "frac": round(ach / PEAK_HBM_GBS, 4)}},
     }
-    log(f"mat_pc fp32: {dt * 1e6:.1f} us/apply, {value:.1f} Gflop/s, "
-        f"{extra['hbm_gbs_mat_pc']} GB/s; kernels {extra['kernel_us']}; "
-        f"caches flushed: {extra['mat_pc_fp32_cold']}")
-
-    # FP64 operator on the same lattice (context figure)
-    x64 = api.tm_spinor_pack(ctx, b[None], p, api.FP64, 0)
-    y64 = api.new_field(p, api.FP64)
-    t64 = time_launches(torch, lambda: api.tm_mat_pc(ctx, y64, x64, g, api.FP64, api.ASYM, 0),
-                        a.kernel_reps)
-    extra["mat_pc_fp64"] = {"us": round(t64 * 1e6, 2), "gflops": round(flops / t64 / 1e9, 1),
-                            "gbs": round((16 * 96 + 5 * 192) * vh / t64 / 1e9, 1)}
-    del x64, y64
-    if not a.no_batch:
-        extra["variants_24x24x24x48_us"] = operator_variants(torch, api, ctx, U, p, a.kernel_reps)
-        v8 = extra["variants_24x24x24x48_us"]["f32_r8"]["asym"]
-        extra["mat_pc_fp32_recon8"] = {"us": v8, "gflops": round(flops / (v8 * 1e-6) / 1e9, 1),
-                                       "gbs": round((16 * 32 + 5 * 96) * vh / (v8 * 1e-6) / 1e9, 1)}
+    log(f"headline: {h['dt'] * 1e6:.1f} us/apply, {value:.1f} Gflop/s, K1 {h['t_k1'] * 1e6:.1f} us, "
+        f"K2 {h['t_k2'] * 1e6:.1f} us ({ach / PEAK_HBM_GBS:.3f} of peak)")
+    cpu = None
+    if not a.headline_only:
+        extra["rates_32x32x32x64"] = {
+            "nd": kernel_rates(torch, api, ctx, g, p, (api.FP64, api.FP16, api.BF16), 20, FLOPS_PER_SITE["nd"])}
+        pd = api.make_params(HEADLINE_DIMS, 0.1615, 0.004, 0.0, api.PLUS)
+        gd = api.Gauge(ctx, Ut, pd, recon=12, precs=(api.FP32,))
+        extra["rates_32x32x32x64"]["deg"] = kernel_rates(torch, api, ctx, gd, pd, (api.FP32,), 20,
+                                                         FLOPS_PER_SITE["deg_asym"])
+        gd.close()
+        g8 = api.Gauge(ctx, Ut, p, recon=8, precs=(api.FP32, api.FP16))
+        extra["rates_32x32x32x64"]["nd_recon8"] = kernel_rates(torch, api, ctx, g8, p, (api.FP32, api.FP16), 20,
+                                                               FLOPS_PER_SITE["nd"], recon=8)
+        g8.close()
+        log(f"32^3x64 rates: {extra['rates_32x32x32x64']}")
+        if not a.no_cg:
+            extra["cg_32x32x32x64_nd"] = cg_comparison(torch, api, ctx, g, p, inputs, a.cg_reps)
     g.close()
     ctx.close()
-    del U
-
-    if a.calib_copy:
-        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
-        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        log("cpu baseline: oracle applies")
-        Uc = inputs.gauge_field(dims, "near_unit", 1002)
-        cpu = cpu_baseline(Uc, b_e, dims, vh)
-        del Uc
-    if not a.no_cg:
-        extra["cg_32x32x32x64_nd"] = cg_comparison(torch, api, inputs, a.cg_reps)
-    if not a.no_batch:
-        extra["batched"] = batched_section(torch, api, inputs)
-        extra.update(force_section(torch, api, inputs))
+    del Ut
+    if not a.headline_only:
+        extra["deg_24x24x24x48"], U2, b2 = section_24(torch, api, inputs, a)
+        if a.calib_copy:
+            # a plain copy of known size: 256 MiB read + 256 MiB written per launch
+            src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        if not a.no_batch:
+            extra["batched"] = batched_section(torch, api, inputs)
+            extra.update(force_section(torch, api, inputs))
+        if not a.no_cpu_baseline:
+            log("cpu baseline: oracle runs")
+            cpu = cpu_baseline(inputs, U3, U2, b2, a.cpu_cg_24)
+        del U2, b2
+    del U3
 
     # context only (another machine): the paper's single-GPU Gflops for this
     # operator at 32^3x64 on a GTX Titan, as its abstract quotes them from
-    # Table 1 (double / single / half; 8-real links for the degenerate single
-    # and half figures)
+    # Table 1 (double / single / half)
     extra["paper_context_gflops_32x32x32x64"] = {
         "degenerate": {"double": 190, "single": 487, "half": 856},
         "non_degenerate": {"double": 163, "single": 516, "half": 879},
         "hardware": "NVIDIA GTX Titan (Kepler)"}
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gflop/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(dt * 1e3, 5),
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(h["dt"] * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (near-unit random SU(3) links, Gaussian source)",
-        "config": {"workload": "tm_mat_pc asymmetric, degenerate, 24^3x48, FP32, 12-real links",
-                   "lattice": "24x24x24x48", "kappa": 0.1615, "mu": 0.004, "recon": 12,
+        "data": "synthetic (near-unit random SU(3) links, Gaussian two-flavour source)",
+        "config": {"workload": WORKLOAD, "lattice": "32x32x32x64", "kappa": HEADLINE["kappa"],
+                   "mu": HEADLINE["mu"], "epsilon": HEADLINE["eps"], "recon": 12,
                    "parallelism": "1 GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }

@@ -293,6 +293,22 @@ int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm
  * TM_XCD_REMAP=0 turns off the XCD-aware block order.                         */
 int tm_set_tuning(tm_ctx *ctx, int enable);
 
+/* Launch planner of the hop kernel (host arithmetic only: no device work,
+ * callable without a GPU).  dyn_bytes receives the dynamic LDS one workgroup
+ * of block_size threads requests so that a compute unit holds at most
+ * wave_cap waves per SIMD (0: no cap; a cap keeps the neighbour spinors the
+ * resident waves share in L2) and at least staging_bytes for staged
+ * neighbours, given the compute unit's LDS (lds_per_cu), the most one
+ * workgroup may use (lds_per_block) and the kernel's static LDS (its function
+ * attributes).  Footprints are planned in multiples of 2560 bytes, so the
+ * dispatcher rounds none of them up.  Returns TM_ERR_LIMIT when no request
+ * meets both limits (the library never dispatches such a launch shape: the
+ * tuner skips it, a forced one fails with TM_ERR_LIMIT) and TM_ERR_ARG on bad
+ * arguments (block_size not a positive multiple of 64, wave_cap outside
+ * 0..8, zero limits, null dyn_bytes).                                        */
+int tm_plan_hop_lds(int block_size, int wave_cap, unsigned staging_bytes, unsigned lds_per_cu,
+                    unsigned lds_per_block, unsigned static_lds, unsigned *dyn_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,8 @@ def lib():
         L.orc_hop.restype = ctypes.c_int
         L.orc_gammas.argtypes = [dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -82,6 +84,11 @@ def _dp(a: np.ndarray):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the C hop's parallel loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def gammas() -> np.ndarray:

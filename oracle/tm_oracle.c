@@ -70,6 +70,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the later parallel loops (timing on one core or on all). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * out = D psi (dagger = 0) or D^+ psi (dagger = 1).  When out_parity is 0 or 1
  * only output sites of that parity are computed and all other output sites are

@@ -72,6 +72,8 @@ _SIGS = {
     "tm_convert": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, P(tm_params), c_int]),
     "tm_force": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_int, c_double,
                          c_int, c_void_p]),
+    "tm_plan_hop_lds": (c_int, [c_int, c_int, ctypes.c_uint, ctypes.c_uint, ctypes.c_uint,
+                                ctypes.c_uint, P(ctypes.c_uint)]),
 }
 
 EXPORTED = tuple(_SIGS)

@@ -42,6 +42,9 @@ struct tm_ctx {
     int force_nr = 0;                  // TM_HOP_NR: 1, 2 or 4 rhs per thread where instantiated (0: default)
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
+    unsigned lds_per_cu = 0;           // from the runtime at context creation
+    unsigned lds_per_block = 0;
+    std::map<std::string, unsigned> static_lds;   // hop variant -> static LDS bytes
 };
 
 struct tm_gauge {
@@ -271,18 +274,37 @@ int zc_for(int target, int Lz)
         if (Lz % d == 0) return d;
     return 0;
 }
-constexpr unsigned kLdsPerCU = 160u << 10;
-// Dynamic LDS of one block may not exceed what a compute unit has minus the
-// kernel's own static LDS (the reduction scratch, a few dozen bytes): a
-// larger request is an invalid dispatch.
-constexpr unsigned kLdsStaticReserve = 1u << 10;
-constexpr unsigned kLdsDynamicMax = kLdsPerCU - kLdsStaticReserve;
-unsigned hop_lds_bytes(const HopCfg &c)
+// Resident-block arithmetic of the wave cap assumes LDS footprints that are
+// multiples of 2560 bytes: a multiple of every LDS allocation unit of CDNA
+// parts (512 and 1280 bytes), so the dispatcher rounds nothing up.
+constexpr unsigned kLdsUnit = 2560;
+constexpr unsigned kLdsPerCUDefault = 160u << 10;   // gfx950, when the runtime cannot be asked
+}  // namespace
+
+// Dynamic LDS of one hop block (see tm_plan_hop_lds in tm.h).
+int tm_plan_hop_lds(int block_size, int wave_cap, unsigned staging_bytes, unsigned lds_per_cu,
+                    unsigned lds_per_block, unsigned static_lds, unsigned *dyn_bytes)
 {
-    if (c.wcap <= 0) return 0;
-    const unsigned blocks = std::max(1u, (unsigned)(4 * c.wcap * 64 / c.bs));   // per compute unit
-    return std::min(((kLdsPerCU / blocks) + 511u) & ~511u, kLdsDynamicMax & ~511u);
+    if (!dyn_bytes || block_size <= 0 || block_size % 64 || wave_cap < 0 || wave_cap > 8 || lds_per_cu == 0 ||
+        lds_per_block == 0)
+        return TM_ERR_ARG;
+    const unsigned long cap = std::min(lds_per_cu, lds_per_block);
+    unsigned long want = staging_bytes;
+    if (wave_cap > 0) {
+        // a compute unit has 4 SIMDs: `blocks` resident blocks of block_size
+        // threads give wave_cap waves per SIMD
+        const unsigned long blocks = std::max(1, 4 * wave_cap * 64 / block_size);
+        const unsigned long f = std::min<unsigned long>(lds_per_cu / blocks, cap) / kLdsUnit * kLdsUnit;
+        // the footprint must admit `blocks` blocks and not one more
+        if (f <= static_lds || (blocks + 1) * f <= lds_per_cu) return TM_ERR_LIMIT;
+        want = std::max(want, f - static_lds);
+    }
+    if (want + static_lds > cap) return TM_ERR_LIMIT;
+    *dyn_bytes = (unsigned)want;
+    return TM_OK;
 }
+
+namespace {
 // LDS of the staged x / y neighbours: six FP32 chunk rows of the block's
 // sites and one y-row either side
 unsigned hop_staging_bytes(int bs, int row)
@@ -353,22 +375,58 @@ void load_tune(tm_ctx *ctx)
 }
 
 hipError_t dispatch_hop(const HopBatch &B, int prec, int nf, int nr, int dagger, int twl, int recon,
-                        const HopCfg &c, bool clv, hipStream_t st)
+                        const HopCfg &c, bool clv, unsigned lds, hipStream_t st, hipFuncAttributes *attr = nullptr)
 {
-    unsigned lds = hop_lds_bytes(c);
+    switch (prec) {
+    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st, attr);
+    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st, attr);
+    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st, attr);
+    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st, attr);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Dynamic LDS of a hop launch: the staged rows (LDS-staged variant) and the
+// wave-cap reservation, planned against the compute unit's LDS (from the
+// runtime) and the variant's own static LDS (from its function attributes).
+// A request that cannot be met is refused (TM_ERR_LIMIT; quiet: without
+// recording an error, for the tuner's candidate filter), never dispatched.
+int hop_lds_plan(tm_ctx *ctx, const HopBatch &B, int prec, int nf, int nr, int dagger, int twl, int recon,
+                 const HopCfg &c, bool clv, unsigned *lds, bool quiet = false)
+{
+    unsigned staging = 0;
     if (c.ldss) {
         int row = 0;
         for (int i = 0; i < B.nprob; i++) row = std::max(row, B.p[i].X[0] / 2);
-        lds = std::max(lds, hop_staging_bytes(c.bs, row));
+        staging = hop_staging_bytes(c.bs, row);
     }
-    if (lds > kLdsDynamicMax) return hipErrorInvalidValue;   // never dispatched
-    switch (prec) {
-    case TM_FP64: return launch_hop_prec<TM_FP64>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
-    case TM_FP32: return launch_hop_prec<TM_FP32>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
-    case TM_FP16: return launch_hop_prec<TM_FP16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
-    case TM_BF16: return launch_hop_prec<TM_BF16>(B, nf, nr, dagger, twl, recon, c.bs, c.lnt, lds, clv, c.ldss, st);
+    *lds = 0;
+    if (c.wcap <= 0 && staging == 0) return TM_OK;
+    char key[96];
+    snprintf(key, sizeof(key), "%d_%d_%d_%d_%d_%d_%d_%d_%d_%d", prec, nf, nr, dagger, twl, recon, c.bs, (int)c.lnt,
+             (int)clv, (int)c.ldss);
+    unsigned static_lds;
+    auto it = ctx->static_lds.find(key);
+    if (it != ctx->static_lds.end()) {
+        static_lds = it->second;
+    } else {
+        hipFuncAttributes attr;
+        memset(&attr, 0, sizeof(attr));
+        const hipError_t e = dispatch_hop(B, prec, nf, nr, dagger, twl, recon, c, clv, 0, nullptr, &attr);
+        if (e != hipSuccess)
+            return quiet ? TM_ERR_HIP : fail(ctx, TM_ERR_HIP, "hop attributes: %s", hipGetErrorString(e));
+        static_lds = (unsigned)attr.sharedSizeBytes;
+        ctx->static_lds[key] = static_lds;
     }
-    return hipErrorInvalidValue;
+    const unsigned cu = ctx->lds_per_cu ? ctx->lds_per_cu : kLdsPerCUDefault;
+    const unsigned blk = ctx->lds_per_block ? ctx->lds_per_block : cu;
+    const int rc = tm_plan_hop_lds(c.bs, c.wcap, staging, cu, blk, static_lds, lds);
+    if (rc != TM_OK && !quiet)
+        return fail(ctx, TM_ERR_LIMIT,
+                    "hop launch: LDS request beyond the compute unit (block %d, wave cap %d, staging %u B, "
+                    "static %u B, %u B per CU, %u B per block)",
+                    c.bs, c.wcap, staging, static_lds, cu, blk);
+    return rc;
 }
 
 // One launch of the fused hop over up to kMaxProblems problems (same
@@ -493,7 +551,8 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     // LDS staging only where the block's rows fit in half a compute unit's LDS
     int xrow = 0;
     for (int i = 0; i < n; i++) xrow = std::max(xrow, calls[i].g->p.dims[0] / 2);
-    auto staging_fits = [&](int bs) { return hop_staging_bytes(bs, xrow) <= kLdsPerCU / 2; };
+    const unsigned lds_cu = ctx->lds_per_cu ? ctx->lds_per_cu : kLdsPerCUDefault;
+    auto staging_fits = [&](int bs) { return hop_staging_bytes(bs, xrow) <= lds_cu / 2; };
     std::vector<HopCfg> cand;
     for (int q : nrs)
         for (HopCfg c : cfg_candidates(prec, nf, q, twl, recon, clv)) {
@@ -524,22 +583,36 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(ctx->stream, &cs);
         if (cs == hipStreamCaptureStatusNone) {
-            // time the instantiated configurations on the real launch (hop
-            // launches are idempotent: out never aliases an input): rhs per
+            // time the instantiated configurations on the real launch: rhs per
             // thread x block size x link-load policy x wave cap in
             // lexicographic site order, then the four best of those with each
-            // brick depth of the site order
+            // brick depth of the site order.  Trials write a scratch output
+            // wherever a call's output is also one of its inputs (an in-place
+            // xpay would otherwise accumulate over the repeated launches).
+            HopCall tc[kMaxProblems];
+            for (int i = 0; i < n; i++) {
+                tc[i] = calls[i];
+                if (tc[i].out == tc[i].x || tc[i].out == tc[i].in) {
+                    char name[48];
+                    snprintf(name, sizeof(name), "tune_out_%d", i);
+                    int rc = TM_OK;
+                    tc[i].out = workspace(ctx, name, spinor_field_bytes(prec, tc[i].g->vh, nf, tc[i].nrhs), &rc);
+                    if (!tc[i].out) return rc;
+                }
+            }
             hipEvent_t e0, e1;
             TM_HIP(ctx, hipEventCreate(&e0));
             TM_HIP(ctx, hipEventCreate(&e1));
             // each trial: one untimed launch, then `reps` timed back to back
             auto trial = [&](const HopCfg &c, int reps, float *ms_per) -> int {
                 HopBatch B;
-                TM_TRY(build_hop_batch(ctx, calls, n, c.nr, c.bs, &B, c.zc));
-                TM_HIP(ctx, dispatch_hop(B, prec, nf, c.nr, dagger, twl, recon, c, clv, ctx->stream));
+                unsigned lds = 0;
+                TM_TRY(build_hop_batch(ctx, tc, n, c.nr, c.bs, &B, c.zc));
+                TM_TRY(hop_lds_plan(ctx, B, prec, nf, c.nr, dagger, twl, recon, c, clv, &lds));
+                TM_HIP(ctx, dispatch_hop(B, prec, nf, c.nr, dagger, twl, recon, c, clv, lds, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
                 for (int r = 0; r < reps; r++)
-                    TM_HIP(ctx, dispatch_hop(B, prec, nf, c.nr, dagger, twl, recon, c, clv, ctx->stream));
+                    TM_HIP(ctx, dispatch_hop(B, prec, nf, c.nr, dagger, twl, recon, c, clv, lds, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e1, ctx->stream));
                 TM_HIP(ctx, hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -548,8 +621,14 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
                 return TM_OK;
             };
             // stage 1: every candidate briefly, lexicographic site order
+            // (candidates whose LDS request the compute unit cannot hold are
+            // skipped)
             std::vector<std::pair<float, HopCfg>> t1;
             for (const HopCfg &c : cand) {
+                HopBatch B;
+                unsigned lds = 0;
+                TM_TRY(build_hop_batch(ctx, tc, n, c.nr, c.bs, &B, c.zc));
+                if (hop_lds_plan(ctx, B, prec, nf, c.nr, dagger, twl, recon, c, clv, &lds, true) != TM_OK) continue;
                 float ms;
                 TM_TRY(trial(c, 4, &ms));
                 t1.push_back({ms, c});
@@ -591,8 +670,10 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
     if (cfg.ldss) cfg.zc = 0;
     if (ctx->force_wcap >= 0) cfg.wcap = ctx->force_wcap;
     HopBatch B;
+    unsigned lds = 0;
     TM_TRY(build_hop_batch(ctx, calls, n, cfg.nr, cfg.bs, &B, cfg.zc));
-    TM_HIP(ctx, dispatch_hop(B, prec, nf, cfg.nr, dagger, twl, recon, cfg, clv, ctx->stream));
+    TM_TRY(hop_lds_plan(ctx, B, prec, nf, cfg.nr, dagger, twl, recon, cfg, clv, &lds));
+    TM_HIP(ctx, dispatch_hop(B, prec, nf, cfg.nr, dagger, twl, recon, cfg, clv, lds, ctx->stream));
     TM_TRY(finish_reductions(ctx, B.p, n));
     return TM_OK;
 }
@@ -765,6 +846,18 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     // Without a device the context still validates arguments (every check
     // runs before the first HIP call); device work then fails with TM_ERR_HIP.
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    if (c->device >= 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) ==
+                hipSuccess && v > 0)
+            c->lds_per_cu = (unsigned)v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, c->device) == hipSuccess && v > 0)
+            c->lds_per_block = (unsigned)v;
+        else if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess &&
+                 v > 0)
+            c->lds_per_block = (unsigned)v;
+        (void)hipGetLastError();
+    }
     const char *e = getenv("TM_XCD_REMAP");
     if (e) c->xcd_remap = atoi(e);
     e = getenv("TM_HOP_BS");

@@ -14,9 +14,12 @@ hipError_t spinor_unpack(int prec, void *dst, SpinorPtr src, const int *X, uint3
 hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t vh, int nrhs,
                        Twist tw, int inverse, hipStream_t st, const void *clov = nullptr);
 
+// Launch the hop variant selected by the arguments, or, when attr is not
+// null, only fill attr with its function attributes (static LDS, registers).
 template <int P>
 hipError_t launch_hop_prec(const HopBatch &B, int nf, int nr, int dagger, int twl, int recon,
-                           int bs, bool lnt, unsigned lds, bool clv, bool ldss, hipStream_t st);
+                           int bs, bool lnt, unsigned lds, bool clv, bool ldss, hipStream_t st,
+                           hipFuncAttributes *attr = nullptr);
 // clover blocks of both parities (FP64 and / or FP32 destinations, nullable)
 hipError_t clover_build(void *const *d64, void *const *d32, const void *links, const int *X, uint32_t vh,
                         double kc, double shift, int *bad, hipStream_t st);

@@ -724,29 +724,31 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
 
 // Host-side dispatch over the compile-time variants built for precision P.
 
+// attr != null: report the variant's attributes instead of launching it
+#define TM_HOP_RUN(KERNEL)                                                                        \
+    do {                                                                                          \
+        if (attr) return hipFuncGetAttributes(attr, reinterpret_cast<const void *>(&KERNEL));     \
+        hipLaunchKernelGGL((KERNEL), dim3(B.total_blocks), dim3(bs), lds, st, B);                  \
+        return hipGetLastError();                                                                 \
+    } while (0)
+
 #define TM_HOP_CASE(P, NF, NR, DAG, TWL, RECON, LNT, BS)                                          \
     if (!clv && !ldss && nf == NF && nr == NR && dagger == DAG && twl == TWL && recon == RECON &&  \
         lnt == LNT && bs == BS) {                                                                   \
-        hipLaunchKernelGGL((hop_kernel<P, NF, NR, DAG, TWL, RECON, LNT, BS>), dim3(B.total_blocks), \
-                           dim3(BS), lds, st, B);                                                   \
-        return hipGetLastError();                                                                   \
+        TM_HOP_RUN((hop_kernel<P, NF, NR, DAG, TWL, RECON, LNT, BS>));                             \
     }
 
 // twisted-clover epilogues (FP64 / FP32, one rhs per thread, no twist-on-load)
 #define TM_HOP_CASE_CLV(P, NF, DAG, RECON, LNT, BS)                                                 \
     if (clv && nf == NF && nr == 1 && dagger == DAG && twl == 0 && recon == RECON && lnt == LNT &&  \
         bs == BS) {                                                                                 \
-        hipLaunchKernelGGL((hop_kernel<P, NF, 1, DAG, false, RECON, LNT, BS, true>),                \
-                           dim3(B.total_blocks), dim3(BS), lds, st, B);                             \
-        return hipGetLastError();                                                                   \
+        TM_HOP_RUN((hop_kernel<P, NF, 1, DAG, false, RECON, LNT, BS, true>));                       \
     }
 // LDS-staged x / y neighbours (FP32, one flavour, one rhs, 12-real links)
 #define TM_HOP_CASE_LDSS(P, DAG, LNT, BS)                                                          \
     if (ldss && !clv && nf == 1 && nr == 1 && dagger == DAG && twl == 0 && recon == 12 &&          \
         lnt == LNT && bs == BS) {                                                                   \
-        hipLaunchKernelGGL((hop_kernel<P, 1, 1, DAG, false, 12, LNT, BS, false, true>),             \
-                           dim3(B.total_blocks), dim3(BS), lds, st, B);                             \
-        return hipGetLastError();                                                                   \
+        TM_HOP_RUN((hop_kernel<P, 1, 1, DAG, false, 12, LNT, BS, false, true>));                    \
     }
 #define TM_HOP_CASES_LDSS(P, BS)                                               \
     TM_HOP_CASE_LDSS(P, 0, true, BS) TM_HOP_CASE_LDSS(P, 1, true, BS)          \
@@ -774,7 +776,7 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
     template <>                                                                                \
     hipError_t launch_hop_prec<P>(const HopBatch &B, int nf, int nr, int dagger, int twl,      \
                                   int recon, int bs, bool lnt, unsigned lds, bool clv,         \
-                                  bool ldss, hipStream_t st)                                   \
+                                  bool ldss, hipStream_t st, hipFuncAttributes *attr)          \
     {                                                                                          \
         if constexpr (P == TM_FP32) {                                                          \
             TM_HOP_CASES_LDSS(P, 256)                                                          \

@@ -5,6 +5,7 @@ import numpy as np
 from oracle import oracle as O
 
 TOL = {0: 1e-12, 1: 1e-5, 2: 5e-3, 3: 5e-3}      # FP64, FP32, FP16, BF16 (norm-wise relative)
+RES_TOL = 1e-10                                   # true FP64 residual of every solve
 
 
 def rel(a, b):
@@ -56,3 +57,19 @@ def oracle_dslash(p, U, inp, out_parity, dagger, twl, epi, x, k):
     if epi == 5:
         return x + k * A
     raise ValueError(epi)
+
+
+def oracle_normal_residual(op, U, x_e, b_e, pc, solution="mat"):
+    """|c - M^+ M x| / |c| with c = M^+ b (solution "mat") or c = b, all by the oracle."""
+    c = O.mat_pc(op, U, b_e, pc, dagger=True) if solution == "mat" else b_e
+    return np.linalg.norm(c - O.normal_op(op, U, x_e, pc)) / np.linalg.norm(c)
+
+
+def check_solve(op, U, x_e, b_e, pc, reported, solution="mat"):
+    """A GPU solution's normal residual recomputed by the oracle is at most the
+    solve tolerance and equals the residual the library reported (1e-3
+    relative: both are FP64, only the summation order differs)."""
+    r = oracle_normal_residual(op, U, x_e, b_e, pc, solution)
+    assert r <= RES_TOL, r
+    assert abs(r - reported) <= 1e-3 * r, (r, reported)
+    return r

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1311_4462_amd import inputs
-from tests.gpu_util import TOL, from_native, oparams, oracle_dslash, rel, to_native
+from tests.gpu_util import TOL, check_solve, from_native, oparams, oracle_dslash, rel, to_native
 
 pytestmark = pytest.mark.gpu
 
@@ -96,8 +96,7 @@ def test_clover_prepare_reconstruct_and_cg(api, ctx, pc):
         r = api.tm_cg(ctx, x, bh, g, pc=pc, tol=1e-10, inner=inner)[0]
         assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
         xe = from_native(api, ctx, x, p, 0, 0)[0]
-        c = O.mat_pc(op, U, bh_ref, pcs, dagger=True)
-        assert rel(O.normal_op(op, U, xe, pcs), c) <= 1.5e-10
+        check_solve(op, U, xe, bh_ref, pcs, r["true_rel_res_normal"])
     xo = api.new_field(p, 0)
     api.tm_reconstruct_odd(ctx, xo, x, bo, g, 0)
     psi = xe + from_native(api, ctx, xo, p, 0, 1)[0]
@@ -114,8 +113,8 @@ def test_clover_graph_cg_and_full_solve(api, ctx):
     x = api.new_field(p, 0)
     r = api.tm_cg(ctx, x, be, g, pc=1, tol=1e-10, inner=1, graph_iters=8)[0]
     assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
-    c = O.mat_pc(op, U, O.project(b, dims, 0), "sym", dagger=True)
-    assert rel(O.normal_op(op, U, from_native(api, ctx, x, p, 0, 0)[0], "sym"), c) <= 1.5e-10
+    check_solve(op, U, from_native(api, ctx, x, p, 0, 0)[0], O.project(b, dims, 0), "sym",
+                r["true_rel_res_normal"])
     for solution in (0, 1):
         xe, xo = api.new_field(p, 0), api.new_field(p, 0)
         rr = api.tm_solve(ctx, xe, xo, be, bo, g, solution=solution, pc=1, tol=1e-11)[0]
@@ -162,7 +161,6 @@ def test_clover_batched_uneven_lattices(api, ctx):
     for i in range(2):
         x = from_native(api, ctx, xs[i], gs[i].params, 0, 0, 2)
         for r in range(2):
-            c = O.mat_pc(ops[i], Us[i], bn[i][r], "sym", dagger=True)
-            assert rel(O.normal_op(ops[i], Us[i], x[r], "sym"), c) <= 1.5e-10
+            check_solve(ops[i], Us[i], x[r], bn[i][r], "sym", res[2 * i + r]["true_rel_res_normal"])
     for g in gs:
         g.close()
