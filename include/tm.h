@@ -42,6 +42,9 @@
  *   Canonical (host-side exchange) layout, complex128, full lattice:
  *       spinor [nrhs][lex][nf][4][3], links [mu][lex][3][3] (row-major).
  *
+ * Enumerated arguments are passed as int holding a value of the named enum
+ * (prec: tm_prec, pc: tm_pc, epi: tm_epilogue); other values are rejected.
+ *
  * Errors: every call returns TM_OK (0), an error (< 0) or the warning
  * TM_NOT_CONVERGED (> 0).  Nothing aborts and no exception crosses the ABI.
  * Arguments are validated before any device work; tm_last_error() returns a
@@ -129,8 +132,19 @@ typedef struct {
     int use_x0;           /* 1: x holds the initial guess                       */
     int nrhs;             /* right-hand sides solved together (>= 1)            */
     int graph_iters;      /* > 0: capture this many iterations in a hipGraph    */
-    int check_every;      /* host convergence check period (0 -> 1)             */
+    int check_every;      /* iterations between host convergence checks (eager
+                             solves; 0 -> 8).  Every iteration is gated on the
+                             device by the convergence state, so iterations
+                             enqueued after convergence do nothing and the
+                             iteration count is exact for any period.        */
     int solution;         /* tm_solution                                        */
+    double stall_factor;  /* mixed: a reliable update whose true |r| is not
+                             below stall_factor times the |r| of the previous
+                             update made no progress (0 -> 1)                 */
+    int max_stalls;       /* mixed: after this many consecutive updates without
+                             progress the solve continues from its x with the
+                             next wider inner precision (FP16/BF16 -> FP32 ->
+                             FP64); 0 -> 3, < 0: never                        */
 } tm_cg_params;
 
 typedef struct {
@@ -142,6 +156,11 @@ typedef struct {
     double true_rel_res_full;     /* tm_solve: |b - M x| / |b| (MATDAG_MAT:
                                      |b - M^+M x| / |b|) over both parities;
                                      tm_cg: -1                                    */
+    int precision_fallbacks;      /* inner-precision promotions after stalls     */
+    int history_len;              /* entries of res_history (<= 16)              */
+    double res_history[16];       /* iterated |r| / |M^+b| of this rhs's last
+                                     history_len iterations, oldest first (the
+                                     precision of the inner iterations)          */
 } tm_cg_result;
 
 typedef struct {
@@ -178,52 +197,52 @@ int tm_gauge_create(tm_ctx *ctx, tm_gauge **g, const void *links_dev, const tm_p
                     int recon, unsigned prec_mask);
 int tm_gauge_destroy(tm_gauge *g);
 /* Device bytes held by the packed links of one precision (0 if not built).    */
-size_t tm_gauge_bytes(const tm_gauge *g, tm_prec prec);
+size_t tm_gauge_bytes(const tm_gauge *g, int prec);
 
 /* Bytes of one parity of a native spinor field (all rhs, flavours, scales).   */
-size_t tm_spinor_bytes(const tm_params *p, tm_prec prec, int nrhs);
+size_t tm_spinor_bytes(const tm_params *p, int prec, int nrhs);
 
 /* Canonical complex128 full-lattice field [nrhs][V][nf][4][3] (device) <->
  * native field of one parity.  Unpack writes only the sites of that parity.
  * basis (tm_basis) is the spin basis of the canonical field; the conversion
  * is applied in FP64 on the way (Sec. 2, converting routines).               */
 int tm_spinor_pack(tm_ctx *ctx, void *dst_native, const void *src_canonical,
-                   const tm_params *p, tm_prec prec, int parity, int nrhs, int basis);
+                   const tm_params *p, int prec, int parity, int nrhs, int basis);
 int tm_spinor_unpack(tm_ctx *ctx, void *dst_canonical, const void *src_native,
-                     const tm_params *p, tm_prec prec, int parity, int nrhs, int basis);
+                     const tm_params *p, int prec, int parity, int nrhs, int basis);
 
 /* Fused hop (Sec. 2.1: the hop fused with its local epilogue): out (parity out_parity) = epilogue of
  * D in or D^+ in (in has the other parity).  twist_on_load = 1 applies R^-1
  * (R^-+ if dagger) to every neighbour before the hop, i.e. A = D R^-1 in.
  * x may be NULL for TM_EPI_NONE / TM_EPI_TWINV.  All fields share prec.       */
-int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
-              int out_parity, int dagger, int twist_on_load, tm_epilogue epi,
+int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int prec,
+              int out_parity, int dagger, int twist_on_load, int epi,
               const void *x, double k, int nrhs);
 
 /* Preconditioned operator of Eq. (2.2) (TM_PC_ASYM) or Eq. (2.3) (TM_PC_SYM),
  * or its dagger, on even fields: two fused hop kernels with an odd temporary
  * held by the context.  out_e and in_e must not alias.                        */
-int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, tm_prec prec,
-              tm_pc pc, int dagger, int nrhs);
+int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, int prec,
+              int pc, int dagger, int nrhs);
 
 /* out = R^-1 in (R^-+ in if dagger) on one parity; inverse = 0 gives R, R^+.
  * The twist is site-local: uniform for twisted mass, the site's clover blocks
  * of that parity for twisted clover.                                          */
-int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
+int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int prec,
              int parity, int dagger, int inverse, int nrhs);
-int tm_twist_inv(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
+int tm_twist_inv(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int prec,
                  int parity, int dagger, int nrhs);
 
 /* Right-hand side of Eq. (2.2) / (2.3): bhat_e = b_e + kappa D_eo R_oo^-1 b_o
  * (asym), R_ee^-1 times that (sym).  (The printed equations omit the kappa
  * that the kappa^2 of their left-hand side requires.)                         */
 int tm_prepare(tm_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o, const tm_gauge *g,
-               tm_prec prec, tm_pc pc, int nrhs);
+               int prec, int pc, int nrhs);
 
 /* Odd half of the solution (Eq. 2.4 read for the unpreconditioned even
  * solution): x_o = R_oo^-1 (b_o + kappa D_oe x_e).                            */
 int tm_reconstruct_odd(tm_ctx *ctx, void *x_o, const void *x_e, const void *b_o,
-                       const tm_gauge *g, tm_prec prec, int nrhs);
+                       const tm_gauge *g, int prec, int nrhs);
 
 /* CG on the normal equations of the preconditioned operator (NORMOP_PC solve,
  * Sec. 2.2): M^+ M x = M^+ b (solution TM_SOLUTION_MAT) or M^+ M x = b
@@ -263,12 +282,12 @@ int tm_solve(tm_ctx *ctx, void *x_e, void *x_o, const void *b_e, const void *b_o
 
 /* Native-field BLAS used by the solvers, exposed for tests and clients.
  * Results are written to host memory (synchronous).                           */
-int tm_norm2(tm_ctx *ctx, double *out_host, const void *x, const tm_params *p, tm_prec prec,
+int tm_norm2(tm_ctx *ctx, double *out_host, const void *x, const tm_params *p, int prec,
              int nrhs);
 int tm_dot(tm_ctx *ctx, double *out_host /* 2*nrhs: re, im */, const void *x, const void *y,
-           const tm_params *p, tm_prec prec, int nrhs);
+           const tm_params *p, int prec, int nrhs);
 /* dst = src converted between precisions (same parity, nrhs).                 */
-int tm_convert(tm_ctx *ctx, void *dst, tm_prec dst_prec, const void *src, tm_prec src_prec,
+int tm_convert(tm_ctx *ctx, void *dst, int dst_prec, const void *src, int src_prec,
                const tm_params *p, int nrhs);
 
 /* Gauge force for S = phi^+ (M^+ M)^-1 phi with M the asymmetric (or
@@ -279,7 +298,7 @@ int tm_convert(tm_ctx *ctx, void *dst, tm_prec dst_prec, const void *src, tm_pre
  * scaled by coeff and added to F_dev if accumulate.  G_dev (nullable, same
  * type and shape): the unconstrained complex gradient with dS = Re tr(G^+ dU). */
 int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm_gauge *g,
-             tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev);
+             int prec, int pc, double coeff, int accumulate, void *G_dev);
 
 /* Autotuner: 1 enables the timing-based choice of the hop launch per kernel
  * variant and shape -- right-hand sides per thread (1, 2 or 4 where they

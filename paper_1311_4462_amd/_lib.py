@@ -26,13 +26,16 @@ class tm_params(ctypes.Structure):
 class tm_cg_params(ctypes.Structure):
     _fields_ = [("pc", c_int), ("tol", c_double), ("maxiter", c_int), ("outer", c_int),
                 ("inner", c_int), ("delta", c_double), ("use_x0", c_int), ("nrhs", c_int),
-                ("graph_iters", c_int), ("check_every", c_int), ("solution", c_int)]
+                ("graph_iters", c_int), ("check_every", c_int), ("solution", c_int),
+                ("stall_factor", c_double), ("max_stalls", c_int)]
 
 
 class tm_cg_result(ctypes.Structure):
     _fields_ = [("iters", c_int), ("reliable_updates", c_int),
                 ("true_rel_res_normal", c_double), ("true_rel_res_pc", c_double),
-                ("seconds", c_double), ("true_rel_res_full", c_double)]
+                ("seconds", c_double), ("true_rel_res_full", c_double),
+                ("precision_fallbacks", c_int), ("history_len", c_int),
+                ("res_history", c_double * 16)]
 
 
 class tm_solve_params(ctypes.Structure):

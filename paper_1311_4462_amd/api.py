@@ -197,12 +197,13 @@ def tm_reconstruct_odd(ctx, x_o, x_e, b_o, gauge: Gauge, prec, nrhs=1):
 
 
 def _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every,
-               solution=0):
+               solution=0, stall_factor=0.0, max_stalls=0):
     p = tm_cg_params()
     p.solution = solution
     p.pc, p.tol, p.maxiter, p.outer, p.inner = pc, tol, maxiter, FP64, inner
     p.delta, p.use_x0, p.nrhs, p.graph_iters, p.check_every = (delta, int(use_x0), nrhs,
                                                                graph_iters, check_every)
+    p.stall_factor, p.max_stalls = stall_factor, max_stalls
     return p
 
 
@@ -210,13 +211,17 @@ def _results(res, n):
     return [dict(iters=res[i].iters, reliable_updates=res[i].reliable_updates,
                  true_rel_res_normal=res[i].true_rel_res_normal,
                  true_rel_res_pc=res[i].true_rel_res_pc, seconds=res[i].seconds,
-                 true_rel_res_full=res[i].true_rel_res_full) for i in range(n)]
+                 true_rel_res_full=res[i].true_rel_res_full,
+                 precision_fallbacks=res[i].precision_fallbacks,
+                 res_history=list(res[i].res_history[:res[i].history_len])) for i in range(n)]
 
 
 def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64, delta=0.0,
-          use_x0=False, nrhs=1, graph_iters=0, check_every=1, solution=SOLUTION_MAT):
+          use_x0=False, nrhs=1, graph_iters=0, check_every=0, solution=SOLUTION_MAT,
+          stall_factor=0.0, max_stalls=0):
     """CG on the normal equations of the preconditioned operator; x_e, b_e FP64 native."""
-    p = _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every, solution)
+    p = _cg_params(pc, tol, maxiter, inner, delta, use_x0, nrhs, graph_iters, check_every, solution,
+                   stall_factor, max_stalls)
     res = (tm_cg_result * nrhs)()
     rc = ctx.check(lib().tm_cg(ctx.h, _ptr(x_e), _ptr(b_e), gauge.h, ctypes.byref(p), res), "tm_cg")
     out = _results(res, nrhs)
@@ -226,7 +231,7 @@ def tm_cg(ctx, x_e, b_e, gauge: Gauge, pc=ASYM, tol=1e-10, maxiter=5000, inner=F
 
 
 def tm_cg_batched(ctx, gauges, xs, bs, nrhs, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64,
-                  delta=0.0, graph_iters=0, check_every=1, solution=SOLUTION_MAT):
+                  delta=0.0, graph_iters=0, check_every=0, solution=SOLUTION_MAT):
     n = len(gauges)
     p = _cg_params(pc, tol, maxiter, inner, delta, False, nrhs[0], graph_iters, check_every, solution)
     ga = (ctypes.c_void_p * n)(*[g.h.value for g in gauges])
@@ -245,7 +250,7 @@ def tm_cg_batched(ctx, gauges, xs, bs, nrhs, pc=ASYM, tol=1e-10, maxiter=5000, i
 
 def tm_solve(ctx, x_e, x_o, b_e, b_o, gauge: Gauge, solution=SOLUTION_MAT,
              solve_type=SOLVE_NORMOP_PC, pc=ASYM, tol=1e-10, maxiter=5000, inner=FP64, delta=0.0,
-             nrhs=1, graph_iters=0, check_every=1):
+             nrhs=1, graph_iters=0, check_every=0):
     """Full-system solve M x = b or M^+ M x = b; all four fields FP64 native."""
     p = tm_solve_params()
     p.cg = _cg_params(pc, tol, maxiter, inner, delta, False, nrhs, graph_iters, check_every)

@@ -1,6 +1,7 @@
 // Host runtime behind include/tm.h: contexts, packed gauge fields, argument
 // validation, operator composition (Eqs. 2.2 - 2.4) and the CG drivers.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -16,6 +17,24 @@
 #include "tm_fields.h"
 
 using namespace twm;
+
+namespace {
+// Named ranges of host-side work for profilers (roctx; next to no cost
+// without a profiler attached): the solver stages, one open at a time.
+struct Phase {
+    bool open = false;
+    void enter(const char *name)
+    {
+        if (open) roctxRangePop();
+        roctxRangePushA(name);
+        open = true;
+    }
+    ~Phase()
+    {
+        if (open) roctxRangePop();
+    }
+};
+}  // namespace
 
 // ------------------------------------------------------------------ objects
 
@@ -529,7 +548,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             if (!cl) return fail(ctx, TM_ERR_PREC, "clover term not built in precision %d", prec);
             TM_HIP(ctx, twist_apply(prec, nf, sptr(tmp, prec, c.g->vh, nf, c.nrhs),
                                     sptr(c.in, prec, c.g->vh, nf, c.nrhs), c.g->vh, c.nrhs,
-                                    make_twist(c.g->p, c.dagger), 1, ctx->stream, cl));
+                                    make_twist(c.g->p, c.dagger), 1, ctx->stream, cl, ctx->gate));
             pre[i] = c;
             pre[i].in = tmp;
             pre[i].twl = 0;
@@ -579,7 +598,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             if (c.bs == want.bs && c.lnt == want.lnt && c.wcap == 0 && c.nr == want.nr) cfg = want;
     } else if (it != ctx->tuned.end()) {
         cfg = cfg_decode(it->second);
-    } else if (ctx->tuning && cand.size() > 1) {
+    } else if (ctx->tuning && cand.size() > 1 && !ctx->gate) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(ctx->stream, &cs);
         if (cs == hipStreamCaptureStatusNone) {
@@ -1000,20 +1019,20 @@ int tm_gauge_destroy(tm_gauge *g)
     return TM_OK;
 }
 
-size_t tm_gauge_bytes(const tm_gauge *g, tm_prec prec)
+size_t tm_gauge_bytes(const tm_gauge *g, int prec)
 {
     if (!g || !valid_prec(prec) || !g->links[prec][0]) return 0;
     return 2 * gauge_parity_bytes(prec, g->recon, g->vh);
 }
 
-size_t tm_spinor_bytes(const tm_params *p, tm_prec prec, int nrhs)
+size_t tm_spinor_bytes(const tm_params *p, int prec, int nrhs)
 {
     if (!p || !valid_prec(prec) || nrhs < 1) return 0;
     if (check_params(nullptr, p) != TM_OK) return 0;
     return spinor_field_bytes(prec, half_volume(*p), nflav(*p), nrhs);
 }
 
-int tm_spinor_pack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, tm_prec prec,
+int tm_spinor_pack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, int prec,
                    int parity, int nrhs, int basis)
 {
     if (!ctx) return TM_ERR_ARG;
@@ -1030,7 +1049,7 @@ int tm_spinor_pack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, 
     return TM_OK;
 }
 
-int tm_spinor_unpack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, tm_prec prec,
+int tm_spinor_unpack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p, int prec,
                      int parity, int nrhs, int basis)
 {
     if (!ctx) return TM_ERR_ARG;
@@ -1047,8 +1066,8 @@ int tm_spinor_unpack(tm_ctx *ctx, void *dst, const void *src, const tm_params *p
     return TM_OK;
 }
 
-int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec,
-              int out_parity, int dagger, int twist_on_load, tm_epilogue epi, const void *x,
+int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int prec,
+              int out_parity, int dagger, int twist_on_load, int epi, const void *x,
               double k, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
@@ -1065,8 +1084,8 @@ int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec
     return hop1(ctx, c);
 }
 
-int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, tm_prec prec,
-              tm_pc pc, int dagger, int nrhs)
+int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, int prec,
+              int pc, int dagger, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_gauge_prec(ctx, g, prec));
@@ -1077,7 +1096,7 @@ int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, tm_
     return mat_pc_batch(ctx, &g, &out_e, &in_e, &nrhs, 1, prec, pc, dagger ? 1 : 0, FIN_NONE, nullptr);
 }
 
-int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec, int parity,
+int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int prec, int parity,
              int dagger, int inverse, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
@@ -1092,14 +1111,14 @@ int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec 
     return TM_OK;
 }
 
-int tm_twist_inv(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, tm_prec prec, int parity,
+int tm_twist_inv(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int prec, int parity,
                  int dagger, int nrhs)
 {
     return tm_twist(ctx, out, in, g, prec, parity, dagger, 1, nrhs);
 }
 
 int tm_prepare(tm_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o, const tm_gauge *g,
-               tm_prec prec, tm_pc pc, int nrhs)
+               int prec, int pc, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_gauge_prec(ctx, g, prec));
@@ -1113,7 +1132,7 @@ int tm_prepare(tm_ctx *ctx, void *bhat_e, const void *b_e, const void *b_o, cons
 }
 
 int tm_reconstruct_odd(tm_ctx *ctx, void *x_o, const void *x_e, const void *b_o, const tm_gauge *g,
-                       tm_prec prec, int nrhs)
+                       int prec, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_gauge_prec(ctx, g, prec));
@@ -1141,7 +1160,7 @@ static int reduce_to_host(tm_ctx *ctx, int op, int prec, const tm_params *p, con
     return TM_OK;
 }
 
-int tm_norm2(tm_ctx *ctx, double *out_host, const void *x, const tm_params *p, tm_prec prec, int nrhs)
+int tm_norm2(tm_ctx *ctx, double *out_host, const void *x, const tm_params *p, int prec, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_params(ctx, p));
@@ -1152,7 +1171,7 @@ int tm_norm2(tm_ctx *ctx, double *out_host, const void *x, const tm_params *p, t
 }
 
 int tm_dot(tm_ctx *ctx, double *out_host, const void *x, const void *y, const tm_params *p,
-           tm_prec prec, int nrhs)
+           int prec, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_params(ctx, p));
@@ -1162,7 +1181,7 @@ int tm_dot(tm_ctx *ctx, double *out_host, const void *x, const void *y, const tm
     return reduce_to_host(ctx, OP_DOT, prec, p, x, y, nrhs, out_host, 2 * nrhs);
 }
 
-int tm_convert(tm_ctx *ctx, void *dst, tm_prec dst_prec, const void *src, tm_prec src_prec,
+int tm_convert(tm_ctx *ctx, void *dst, int dst_prec, const void *src, int src_prec,
                const tm_params *p, int nrhs)
 {
     if (!ctx) return TM_ERR_ARG;
@@ -1319,6 +1338,10 @@ int true_residual(tm_ctx *ctx, std::vector<CGProblem> &pr, int pc, int rp, void 
     return launch_blas_batch(ctx, OP_RESIDUAL, TM_FP64, rp, pr[0].g->nf, calls, n);
 }
 
+// cg_run's internal status: a mixed solve stopped on stalled reliable updates
+// (x holds the accumulated solution; the caller continues in a wider format)
+constexpr int kStalled = 100;
+
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -1345,9 +1368,11 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     // (measured: BF16 at 0.002 never converges), so delta is raised to it.
     const double delta_floor = inner == TM_FP32 ? 1e-5 : (inner == TM_FP16 ? 2e-3 : 1e-2);
     const double delta = std::max(par->delta > 0 ? par->delta : (inner == TM_FP32 ? 1e-3 : 1e-2), delta_floor);
-    const int check_every = std::max(1, par->check_every);
+    const int check_every = par->check_every > 0 ? par->check_every : 8;
     const int nf = pr[0].g->nf;
 
+    Phase phase;
+    phase.enter("tm_cg: setup");
     for (int i = 0; i < n; i++) TM_TRY(cg_setup_vectors(ctx, pr[i], i, inner));
     // Every buffer an iteration touches exists before any graph capture: the
     // reduction slots at their largest size and the odd temporaries.
@@ -1412,6 +1437,8 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
                 CGScalars s{};
                 s.stop2 = par->tol * par->tol * pr[i].cc[r];
                 s.active = pr[i].cc[r] > 0 ? 1 : 0;
+                const double sf = par->stall_factor > 0 ? par->stall_factor : 1.0;
+                s.stall_f2 = sf * sf;
                 hs[off + r] = s;
             }
             TM_HIP(ctx, hipMemcpyAsync(pr[i].cg, hs + off, pr[i].nrhs * sizeof(CGScalars),
@@ -1450,8 +1477,6 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
                                 pr[i].cg, pr[i].dres};
         TM_TRY(launch_blas_batch(ctx, OP_RESIDUAL, TM_FP64, lp, nf, calls, n));
     }
-    // true_valid: the scalars' rr is the true FP64 residual of the current x
-    bool true_valid = true;
 
     // One CG iteration over all problems, every stage one batched launch:
     // M p (|M p|^2 -> alpha), M^+ M p, x += alpha p / r -= alpha A p (|r|^2 -> beta).
@@ -1482,34 +1507,75 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         return true_residual(ctx, pr, pc, lp, rv, nullptr, FIN_RELIABLE);
     };
 
-    // Mixed precision with captured iterations: the reliable update is decided
-    // on the device every iteration and its launches are gated by that flag.
-    int *gate = nullptr;
-    const bool device_updates = mixed && par->graph_iters > 0;
-    if (device_updates) {
+    // Device-side control of every iteration (eager or captured):
+    //   flags[0]  reliable-update gate (mixed: decided on the device each
+    //             iteration, its launches gated by it)
+    //   flags[1]  number of reliable updates taken
+    //   flags[2]  run flag: some rhs still iterates; every launch of an
+    //             iteration is gated by it, so iterations enqueued after
+    //             convergence do nothing
+    //   flags[3]  iterations that ran
+    int *flags = nullptr;
+    {
         int rc = TM_OK;
-        gate = (int *)workspace(ctx, "cg_gate", 256, &rc);
-        if (!gate) return rc;
-        TM_HIP(ctx, hipMemsetAsync(gate, 0, 256, ctx->stream));
+        flags = (int *)workspace(ctx, "cg_flags", 256, &rc);
+        if (!flags) return rc;
+        TM_HIP(ctx, hipMemsetAsync(flags, 0, 256, ctx->stream));
     }
-    auto iteration_device_updates = [&]() -> int {
-        TM_TRY(iteration_core());
-        DecideArgs D;
-        memset(&D, 0, sizeof(D));
-        D.nprob = n;
-        for (int i = 0; i < n; i++) {
-            D.nrhs[i] = pr[i].nrhs;
-            D.cg[i] = pr[i].cg;
+    int *const upd_gate = flags, *const upd_count = flags + 1, *const run_flag = flags + 2,
+              *const iter_count = flags + 3;
+    RunArgs RA;
+    memset(&RA, 0, sizeof(RA));
+    DecideArgs D;
+    memset(&D, 0, sizeof(D));
+    RA.nprob = D.nprob = n;
+    for (int i = 0; i < n; i++) {
+        RA.nrhs[i] = D.nrhs[i] = pr[i].nrhs;
+        RA.cg[i] = D.cg[i] = pr[i].cg;
+    }
+    RA.with_pending = mixed ? 1 : 0;
+    RA.run = run_flag;
+    RA.iters = iter_count;
+    D.delta2 = delta * delta;
+    D.gate = upd_gate;
+    D.count = upd_count;
+
+    // Tune every hop the iterations launch before any launch is gated or
+    // captured (the tuner times real launches and is skipped in both cases):
+    // the inner operator and its dagger from p, and for reliable updates the
+    // FP64 normal operator; the scratch vectors written are overwritten by
+    // the first iteration.
+    if (ctx->tuning) {
+        TM_TRY(mat_pc_batch(ctx, gs, mpv, (const void *const *)pv, nr, n, lp, pc, 0, FIN_NONE, nullptr));
+        TM_TRY(mat_pc_batch(ctx, gs, apv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_NONE, nullptr));
+        if (mixed) {
+            void *ys[kMaxProblems], *mids[kMaxProblems];
+            const void *xs[kMaxProblems];
+            for (int i = 0; i < n; i++) {
+                ys[i] = pr[i].y;
+                mids[i] = pr[i].mid;
+                xs[i] = pr[i].c;
+            }
+            TM_TRY(normal_op64(ctx, pr, pc, ys, mids, xs));
         }
-        D.delta2 = delta * delta;
-        D.gate = gate;
-        D.count = gate + 1;
-        TM_HIP(ctx, launch_decide(D, ctx->stream));
-        ctx->gate = gate;
-        const int rc = reliable_update();
+    }
+
+    auto iteration = [&]() -> int {
+        TM_HIP(ctx, launch_run(RA, ctx->stream));
+        ctx->gate = run_flag;
+        int rc = iteration_core();
+        if (rc == TM_OK && mixed) {
+            rc = (launch_decide(D, ctx->stream) == hipSuccess) ? TM_OK
+                                                                : fail(ctx, TM_ERR_HIP, "decide launch");
+            if (rc == TM_OK) {
+                ctx->gate = upd_gate;
+                rc = reliable_update();
+                ctx->gate = run_flag;
+            }
+        }
+        if (rc == TM_OK) rc = xpay();
         ctx->gate = nullptr;
-        TM_TRY(rc);
-        return xpay();
+        return rc;
     };
 
     GraphCache gc;
@@ -1517,14 +1583,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     if (gk > 0) {
         TM_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
         int rc = TM_OK;
-        for (int k = 0; k < gk && rc == TM_OK; k++) {
-            if (device_updates) {
-                rc = iteration_device_updates();
-            } else {
-                rc = iteration_core();
-                if (rc == TM_OK) rc = xpay();
-            }
-        }
+        for (int k = 0; k < gk && rc == TM_OK; k++) rc = iteration();
         ctx->gate = nullptr;
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
@@ -1537,85 +1596,162 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         TM_HIP(ctx, hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0));
     }
 
-    int iters = 0, updates = 0;
+    // Host side: chunks of iterations (one graph, or check_every eager
+    // iterations) are enqueued one ahead of the check of the previous chunk,
+    // whose scalars and flags come back with one small asynchronous copy into
+    // pinned memory; the chunk enqueued speculatively after convergence runs
+    // gated and does nothing.
+    int total_rhs = 0;
+    for (auto &p : pr) total_rhs += p.nrhs;
+    const size_t snap_bytes = (size_t)total_rhs * sizeof(CGScalars) + 4 * sizeof(int);
+    char *snap[2];
+    hipEvent_t snap_ev[2] = {nullptr, nullptr};
+    {
+        int rc = TM_OK;
+        double *h = host_scratch(ctx, 2 * ((snap_bytes + 255) / 256) * 256 / sizeof(double), &rc);
+        if (!h) return rc;
+        snap[0] = (char *)h;
+        snap[1] = snap[0] + (snap_bytes + 255) / 256 * 256;
+        for (int k = 0; k < 2; k++) TM_HIP(ctx, hipEventCreateWithFlags(&snap_ev[k], hipEventDisableTiming));
+    }
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int k = 0; k < 2; k++)
+                if (e[k]) (void)hipEventDestroy(e[k]);
+        }
+    } ev_guard{snap_ev};
+    const int chunk = gk > 0 ? gk : check_every;
+    auto enqueue_chunk = [&](int slot) -> int {
+        if (gk > 0) {
+            TM_HIP(ctx, hipGraphLaunch(gc.exec, ctx->stream));
+        } else {
+            for (int k = 0; k < chunk; k++) TM_TRY(iteration());
+        }
+        size_t off = 0;
+        for (int i = 0; i < n; i++) {
+            TM_HIP(ctx, hipMemcpyAsync(snap[slot] + off, pr[i].cg, pr[i].nrhs * sizeof(CGScalars),
+                                       hipMemcpyDeviceToHost, ctx->stream));
+            off += pr[i].nrhs * sizeof(CGScalars);
+        }
+        TM_HIP(ctx, hipMemcpyAsync(snap[slot] + off, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        TM_HIP(ctx, hipEventRecord(snap_ev[slot], ctx->stream));
+        return TM_OK;
+    };
+    // copy a snapshot into sc / the flag counters
+    int hflags[4] = {0, 0, 0, 0};
     std::vector<std::vector<CGScalars>> sc;
-    TM_TRY(read_scalars(ctx, pr, sc));
-    bool done = false;
-    int status = TM_OK;
+    auto unpack = [&](int slot) {
+        sc.assign(n, {});
+        size_t off = 0;
+        for (int i = 0; i < n; i++) {
+            const CGScalars *c = (const CGScalars *)(snap[slot] + off);
+            sc[i].assign(c, c + pr[i].nrhs);
+            off += pr[i].nrhs * sizeof(CGScalars);
+        }
+        memcpy(hflags, snap[slot] + off, sizeof(hflags));
+    };
     auto all_inactive = [&]() {
         for (int i = 0; i < n; i++)
             for (int r = 0; r < pr[i].nrhs; r++)
-                if (sc[i][r].active || (device_updates && sc[i][r].pending)) return false;
+                if (sc[i][r].active || (mixed && sc[i][r].pending)) return false;
         return true;
     };
-    done = all_inactive();
-    while (!done) {
-        int step = 0;
-        if (gk > 0) {
-            TM_HIP(ctx, hipGraphLaunch(gc.exec, ctx->stream));
-            step = gk;
-        } else if (mixed) {
-            TM_TRY(iteration_core());
-            step = 1;
-        } else {
-            const int m = check_every;
-            for (int k = 0; k < m; k++) {
-                TM_TRY(iteration_core());
-                TM_TRY(xpay());
-            }
-            step = m;
+    const int max_stalls = par->max_stalls == 0 ? 3 : par->max_stalls;
+    phase.enter("tm_cg: iterations");
+    int status = TM_OK;
+    bool stalled = false;
+    long enqueued = 0;            // iterations enqueued (an upper bound of those run)
+    int slot = 0;
+    bool in_flight = false;       // a chunk whose snapshot is not yet read
+    for (;;) {
+        bool launched = false;
+        if (enqueued < par->maxiter) {
+            TM_TRY(enqueue_chunk(slot));
+            enqueued += chunk;
+            launched = true;
         }
-        iters += step;
-        true_valid = false;
-        TM_TRY(read_scalars(ctx, pr, sc));
-        bool need_update = false, bad = false;
+        if (!in_flight) {
+            // the first chunk: nothing to check yet
+            in_flight = launched;
+            slot ^= 1;
+            if (!launched) break;
+            continue;
+        }
+        // check the previous chunk while this one runs
+        const int prev = slot ^ 1;
+        TM_HIP(ctx, hipEventSynchronize(snap_ev[prev]));
+        unpack(prev);
+        bool bad = false, stall = false;
         for (int i = 0; i < n; i++)
             for (int r = 0; r < pr[i].nrhs; r++) {
                 const CGScalars &s = sc[i][r];
                 if (!std::isfinite(s.rr) || !std::isfinite(s.alpha)) bad = true;
-                if (s.pending || (s.active && s.rr < delta * delta * s.maxrr)) need_update = true;
+                if (mixed && max_stalls > 0 && s.stall >= max_stalls) stall = true;
             }
-        if (bad) return fail(ctx, TM_ERR_NAN, "non-finite residual after %d iterations", iters);
-        if (device_updates) {
-            done = all_inactive();
-        } else if (mixed) {
-            if (need_update) {
-                TM_TRY(reliable_update());
-                updates++;
-            }
-            TM_TRY(xpay());
-            if (need_update) {
-                true_valid = true;
+        if (bad) {
+            (void)hipStreamSynchronize(ctx->stream);
+            return fail(ctx, TM_ERR_NAN, "non-finite residual after %d iterations", hflags[3]);
+        }
+        bool done = false;
+        if (stall) {
+            stalled = true;
+            done = true;
+        } else if (all_inactive()) {
+            if (mixed) {
+                done = true;    // the verifying reliable update ran on the device
+            } else {
+                // plain CG: verify with the true residual (after the chunk in
+                // flight, which runs gated), restart from it if it is not small enough
+                TM_TRY(true_residual(ctx, pr, pc, TM_FP64, rv, pv, FIN_STORE_RR));
                 TM_TRY(read_scalars(ctx, pr, sc));
                 done = all_inactive();
+                if (!done) {
+                    // the chunk enqueued above was a no-op: iterate afresh
+                    launched = false;
+                    in_flight = false;
+                }
             }
-        } else if (all_inactive()) {
-            // verify with the true residual; restart from it if it is not small enough
-            TM_TRY(true_residual(ctx, pr, pc, TM_FP64, rv, pv, FIN_STORE_RR));
-            true_valid = true;
-            TM_TRY(read_scalars(ctx, pr, sc));
-            done = all_inactive();
         }
-        if (!done && iters >= par->maxiter) {
+        if (done) break;
+        if (!launched && in_flight && enqueued >= par->maxiter) {
             status = TM_NOT_CONVERGED;
             break;
         }
+        slot ^= 1;
     }
-    if (device_updates) {
-        // updates decided on the device; the last one left x and rr consistent
-        int h[2] = {0, 0};
-        TM_HIP(ctx, hipMemcpyAsync(h, gate, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    // the last snapshot of the device state (all work enqueued so far done)
+    phase.enter("tm_cg: final residuals");
+    TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    TM_TRY(read_scalars(ctx, pr, sc));
+    {
+        TM_HIP(ctx, hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, ctx->stream));
         TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        updates = h[1];
-        true_valid = (status == TM_OK);
     }
-    if (mixed && status == TM_NOT_CONVERGED) {
+    if (status == TM_OK && !stalled && !all_inactive()) status = TM_NOT_CONVERGED;
+    const int iters = hflags[3];
+    const int updates = mixed ? hflags[1] : 0;
+    // mixed: the verifying update left x and rr consistent; plain: the
+    // verification above did
+    bool true_valid = (status == TM_OK && !stalled);
+    if (mixed && (status == TM_NOT_CONVERGED || stalled)) {
         BlasCall acc[kMaxProblems];
         for (int i = 0; i < n; i++)
             acc[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, nullptr, nullptr}, FIN_NONE,
                               nullptr, nullptr};
         TM_TRY(launch_blas_batch(ctx, OP_ACCUM_ZERO, TM_FP64, TM_FP32, nf, acc, n));
         true_valid = false;
+    }
+    if (stalled) {
+        TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        int off = 0;
+        for (int i = 0; i < n; i++)
+            for (int r = 0; r < pr[i].nrhs; r++, off++) {
+                res[off].iters = iters;
+                res[off].reliable_updates = updates;
+            }
+        return kStalled;
     }
     TM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1672,10 +1808,54 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             o.true_rel_res_pc = bb[i][r] > 0 ? std::sqrt(rp[i][r] / bb[i][r]) : 0.0;
             o.seconds = secs;
             o.true_rel_res_full = -1.0;
+            o.precision_fallbacks = 0;
+            // the last iterated residuals of this rhs, oldest first
+            const CGScalars &s = sc[i][r];
+            const int len = std::min(s.niter, kHistory);
+            o.history_len = len;
+            for (int j = 0; j < len; j++) {
+                const double h = s.hist[(s.niter - len + j) % kHistory];
+                o.res_history[j] = pr[i].cc[r] > 0 ? std::sqrt(h / pr[i].cc[r]) : 0.0;
+            }
             if (!std::isfinite(o.true_rel_res_normal)) status = fail(ctx, TM_ERR_NAN, "non-finite residual");
             if (status == TM_OK && o.true_rel_res_normal > par->tol * 1.0000001) status = TM_NOT_CONVERGED;
         }
     return status;
+}
+
+// cg_run with the precision fallback: a mixed solve whose reliable updates
+// stopped making progress continues from its x with the next wider inner
+// format (FP16 / BF16 -> FP32 -> FP64); iterations, updates and time add up.
+int cg_solve(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_cg_result *res)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    tm_cg_params p = *par;
+    int total = 0;
+    for (auto &q : pr) total += q.nrhs;
+    int iters = 0, updates = 0, fallbacks = 0;
+    for (;;) {
+        const int rc = cg_run(ctx, pr, &p, res);
+        if (rc < 0) return rc;
+        iters += res[0].iters;
+        updates += res[0].reliable_updates;
+        if (rc != kStalled) {
+            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            for (int k = 0; k < total; k++) {
+                res[k].iters = iters;
+                res[k].reliable_updates = updates;
+                res[k].precision_fallbacks = fallbacks;
+                res[k].seconds = secs;
+            }
+            return rc;
+        }
+        fallbacks++;
+        int next = (p.inner == TM_FP16 || p.inner == TM_BF16) ? TM_FP32 : TM_FP64;
+        for (auto &q : pr)
+            if (!q.g->links[next][0]) next = TM_FP64;   // the wider format is not built
+        p.inner = next;
+        p.use_x0 = 1;
+        p.maxiter = std::max(1, p.maxiter - res[0].iters);
+    }
 }
 
 int check_cg(tm_ctx *ctx, const tm_gauge *g, const tm_cg_params *par)
@@ -1689,6 +1869,8 @@ int check_cg(tm_ctx *ctx, const tm_gauge *g, const tm_cg_params *par)
     if (par->graph_iters < 0 || par->graph_iters > 256) return fail(ctx, TM_ERR_ARG, "graph_iters in 0..256");
     if (par->solution != TM_SOLUTION_MAT && par->solution != TM_SOLUTION_MATDAG_MAT)
         return fail(ctx, TM_ERR_ARG, "bad solution type");
+    Phase phase;
+    phase.enter("tm_solve");
     TM_TRY(check_gauge_prec(ctx, g, TM_FP64));
     TM_TRY(check_gauge_prec(ctx, g, par->inner));
     return TM_OK;
@@ -1736,7 +1918,7 @@ int tm_cg(tm_ctx *ctx, void *x_e, const void *b_e, const tm_gauge *g, const tm_c
     pr[0].x = x_e;
     pr[0].b = b_e;
     StreamSwap sw(ctx, par->graph_iters > 0);
-    return cg_run(ctx, pr, par, res);
+    return cg_solve(ctx, pr, par, res);
 }
 
 int tm_cg_batched(tm_ctx *ctx, int nproblems, const tm_gauge *const *g, void *const *x_e,
@@ -1761,7 +1943,7 @@ int tm_cg_batched(tm_ctx *ctx, int nproblems, const tm_gauge *const *g, void *co
         pr[i].b = b_e[i];
     }
     StreamSwap sw(ctx, par->graph_iters > 0);
-    return cg_run(ctx, pr, par, res);
+    return cg_solve(ctx, pr, par, res);
 }
 
 namespace {
@@ -1810,8 +1992,11 @@ void add_report(tm_cg_result *acc, const tm_cg_result *r, int nrhs)
     for (int i = 0; i < nrhs; i++) {
         acc[i].iters += r[i].iters;
         acc[i].reliable_updates += r[i].reliable_updates;
+        acc[i].precision_fallbacks += r[i].precision_fallbacks;
         acc[i].true_rel_res_normal = r[i].true_rel_res_normal;
         acc[i].true_rel_res_pc = r[i].true_rel_res_pc;
+        acc[i].history_len = r[i].history_len;
+        for (int j = 0; j < r[i].history_len; j++) acc[i].res_history[j] = r[i].res_history[j];
     }
 }
 
@@ -1835,7 +2020,7 @@ int solve_pc(tm_ctx *ctx, const tm_gauge *g, void *x, const void *b, const tm_so
         pr[0].nrhs = nrhs;
         pr[0].x = x;
         pr[0].b = b;
-        const int rc = cg_run(ctx, pr, &q, r.data());
+        const int rc = cg_solve(ctx, pr, &q, r.data());
         if (rc < 0) return rc;
         add_report(acc, r.data(), nrhs);
         if (rc == TM_NOT_CONVERGED) {
@@ -1873,6 +2058,8 @@ int tm_solve(tm_ctx *ctx, void *x_e, void *x_o, const void *b_e, const void *b_o
         return fail(ctx, TM_ERR_ARG, "bad solve type");
     if (par->solution != TM_SOLUTION_MAT && par->solution != TM_SOLUTION_MATDAG_MAT)
         return fail(ctx, TM_ERR_ARG, "bad solution type");
+    Phase phase;
+    phase.enter("tm_solve");
     const auto t0 = std::chrono::steady_clock::now();
     const int nrhs = par->cg.nrhs;
     const int pc = par->cg.pc;
@@ -1950,7 +2137,7 @@ int tm_solve(tm_ctx *ctx, void *x_e, void *x_o, const void *b_e, const void *b_o
 }
 
 int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm_gauge *g,
-             tm_prec prec, tm_pc pc, double coeff, int accumulate, void *G_dev)
+             int prec, int pc, double coeff, int accumulate, void *G_dev)
 {
     if (!ctx) return TM_ERR_ARG;
     TM_TRY(check_gauge_prec(ctx, g, prec));

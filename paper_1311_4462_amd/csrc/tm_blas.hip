@@ -324,6 +324,25 @@ __global__ void decide_kernel(const DecideArgs D)
     if (need) *D.count += 1;
 }
 
+__global__ void run_kernel(const RunArgs R)
+{
+    if (threadIdx.x != 0) return;
+    int run = 0;
+    for (int i = 0; i < R.nprob; i++)
+        for (int r = 0; r < R.nrhs[i]; r++) {
+            const CGScalars &c = R.cg[i][r];
+            if (c.active || (R.with_pending && c.pending)) run = 1;
+        }
+    *R.run = run;
+    if (run) *R.iters += 1;
+}
+
+hipError_t launch_run(const RunArgs &R, hipStream_t st)
+{
+    hipLaunchKernelGGL(run_kernel, dim3(1), dim3(64), 0, st, R);
+    return hipGetLastError();
+}
+
 hipError_t launch_decide(const DecideArgs &D, hipStream_t st)
 {
     hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, st, D);

@@ -11,8 +11,10 @@ hipError_t spinor_pack(int prec, SpinorPtr dst, const void *src, const int *X, u
                        int nf, int nrhs, int basis, hipStream_t st);
 hipError_t spinor_unpack(int prec, void *dst, SpinorPtr src, const int *X, uint32_t vh, int par,
                          int nf, int nrhs, int basis, hipStream_t st);
+// gate (nullable): the launch does nothing when *gate == 0
 hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t vh, int nrhs,
-                       Twist tw, int inverse, hipStream_t st, const void *clov = nullptr);
+                       Twist tw, int inverse, hipStream_t st, const void *clov = nullptr,
+                       const int *gate = nullptr);
 
 // Launch the hop variant selected by the arguments, or, when attr is not
 // null, only fill attr with its function attributes (static LDS, registers).
@@ -56,6 +58,7 @@ struct BlasBatch {
 hipError_t launch_blas(int op, int pa, int pb, const BlasBatch &B, hipStream_t st);
 hipError_t launch_finish(const FinishBatch &F, hipStream_t st);
 hipError_t launch_decide(const DecideArgs &D, hipStream_t st);
+hipError_t launch_run(const RunArgs &R, hipStream_t st);
 
 // force
 hipError_t force_launch(int prec, int nf, int force_prec, void *F, void *G, const void *gauge0,

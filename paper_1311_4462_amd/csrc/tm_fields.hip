@@ -158,9 +158,10 @@ hipError_t spinor_unpack(int prec, void *dst, SpinorPtr src, const int *X, uint3
 
 template <int P, int NF>
 __global__ void twist_kernel(SpinorPtr out, SpinorPtr in, uint32_t vh, Twist tw, int inverse,
-                             const void *clov)
+                             const void *clov, const int *gate)
 {
     using real = typename Prec<P>::real;
+    if (gate && *gate == 0) return;   // gated launch not needed this iteration
     const uint32_t cb = blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
     if (cb >= vh) return;
@@ -178,13 +179,13 @@ __global__ void twist_kernel(SpinorPtr out, SpinorPtr in, uint32_t vh, Twist tw,
 }
 
 hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t vh, int nrhs,
-                       Twist tw, int inverse, hipStream_t st, const void *clov)
+                       Twist tw, int inverse, hipStream_t st, const void *clov, const int *gate)
 {
     dim3 grid((vh + 255) / 256, nrhs);
 #define TM_TW(P, NF)                                                                            \
     if (prec == P && nf == NF) {                                                                \
         hipLaunchKernelGGL((twist_kernel<P, NF>), grid, dim3(256), 0, st, out, in, vh, tw, inverse, \
-                           clov);                                                               \
+                           clov, gate);                                                         \
         return hipGetLastError();                                                               \
     }
     TM_TW(TM_FP64, 1) TM_TW(TM_FP64, 2) TM_TW(TM_FP32, 1) TM_TW(TM_FP32, 2)

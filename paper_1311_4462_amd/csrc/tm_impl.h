@@ -761,6 +761,7 @@ __device__ __forceinline__ void apply_clover(cx<typename Prec<P>::real> (&v)[NF]
 // ------------------------------------------------------------------ reductions
 
 // CG scalars per right-hand side, device resident.
+constexpr int kHistory = 16;   // iterated residuals kept per rhs (ring)
 struct CGScalars {
     double rr;       // |r|^2 of the iterated residual
     double rr_old;
@@ -769,6 +770,12 @@ struct CGScalars {
     double beta;
     double stop2;    // stop when rr <= stop2
     double maxrr;    // largest rr since the last residual replacement
+    double rr_upd;   // true |r|^2 at the last residual replacement (0: none yet)
+    double stall_f2; // squared stall factor: a replacement whose true |r|^2 is
+                     // not below stall_f2 * rr_upd made no progress
+    double hist[kHistory];   // |r|^2 of the last iterations, hist[i % kHistory]
+    int niter;       // iterations this rhs was active in
+    int stall;       // consecutive replacements without progress
     int active;      // 0 once converged (updates become no-ops)
     int pending;     // converged in the iterated residual, not yet verified
 };
@@ -805,6 +812,20 @@ struct DecideArgs {
     double delta2;
     int *gate;
     int *count;            // number of updates decided (for reporting)
+};
+
+// Device-side run flag of a CG iteration: set when some rhs is still active
+// (or, with reliable updates, awaits its verifying update); every launch of
+// the iteration is gated by it, so iterations enqueued past convergence (the
+// rest of a captured graph, the rest of a host check period) do nothing.
+// iters counts the iterations that ran.
+struct RunArgs {
+    int nprob;
+    int nrhs[kMaxProblems];
+    const CGScalars *cg[kMaxProblems];
+    int with_pending;
+    int *run;
+    int *iters;
 };
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -854,6 +875,8 @@ __device__ void finish_reduce(const Reduce &rd, int v0, int v1, int nblk, double
                     c.rr_old = c.rr;
                     c.rr = s;
                     c.maxrr = fmax(c.maxrr, s);
+                    c.hist[c.niter % kHistory] = s;
+                    c.niter++;
                     if (s <= c.stop2) {
                         c.active = 0;
                         c.pending = 1;
@@ -865,6 +888,16 @@ __device__ void finish_reduce(const Reduce &rd, int v0, int v1, int nblk, double
                 // the residual was replaced by the true one (reliable update):
                 // continue the recurrence with beta = |r_true|^2 / |r_prev|^2
                 CGScalars &c = rd.cg[v];
+                // progress of the true residual from one replacement to the
+                // next, for rhs that were iterating (a converged rhs shares
+                // the replacements of the others without moving)
+                if (c.active || c.pending) {
+                    if (c.rr_upd > 0.0 && s >= c.stall_f2 * c.rr_upd)
+                        c.stall++;
+                    else
+                        c.stall = 0;
+                    c.rr_upd = s;
+                }
                 c.beta = (c.rr_old > 0.0) ? s / c.rr_old : 0.0;
                 c.rr = s;
                 c.maxrr = s;
@@ -879,6 +912,8 @@ __device__ void finish_reduce(const Reduce &rd, int v0, int v1, int nblk, double
                 c.beta = 0.0;
                 c.active = (s > c.stop2) ? 1 : 0;
                 c.pending = 0;
+                c.rr_upd = s;
+                c.stall = 0;
             }
         }
     }
