@@ -1534,6 +1534,7 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         RA.cg[i] = D.cg[i] = pr[i].cg;
     }
     RA.with_pending = mixed ? 1 : 0;
+    RA.maxiter = par->maxiter;
     RA.run = run_flag;
     RA.iters = iter_count;
     D.delta2 = delta * delta;

@@ -333,6 +333,7 @@ __global__ void run_kernel(const RunArgs R)
             const CGScalars &c = R.cg[i][r];
             if (c.active || (R.with_pending && c.pending)) run = 1;
         }
+    if (*R.iters >= R.maxiter) run = 0;
     *R.run = run;
     if (run) *R.iters += 1;
 }

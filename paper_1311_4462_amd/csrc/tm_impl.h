@@ -818,12 +818,14 @@ struct DecideArgs {
 // (or, with reliable updates, awaits its verifying update); every launch of
 // the iteration is gated by it, so iterations enqueued past convergence (the
 // rest of a captured graph, the rest of a host check period) do nothing.
-// iters counts the iterations that ran.
+// iters counts the iterations that ran; once it reaches maxiter the flag
+// stays clear, so a check period never runs past the iteration limit.
 struct RunArgs {
     int nprob;
     int nrhs[kMaxProblems];
     const CGScalars *cg[kMaxProblems];
     int with_pending;
+    int maxiter;
     int *run;
     int *iters;
 };
