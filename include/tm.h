@@ -305,10 +305,13 @@ int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm
  * divide every problem's count; one flavour, 12-real links), block size,
  * link-load policy, cap of resident waves per SIMD, LDS staging (FP32 one
  * flavour), then the four fastest of those in each depth of the brick site
- * order -- cached per context and persisted to $TM_TUNE_CACHE if set;
- * 0 disables (defaults are then used).
+ * order, then the winner with its single-use streams (output stores, xpay
+ * operand and time-neighbour loads) accessed non-temporally -- cached per
+ * context and persisted to $TM_TUNE_CACHE if set; 0 disables (defaults are
+ * then used).
  * Read at context creation, for experiments: TM_HOP_NR, TM_HOP_BS,
- * TM_LINK_NT, TM_HOP_WCAP, TM_HOP_ZC, TM_HOP_LDS fix one of those choices,
+ * TM_LINK_NT, TM_HOP_WCAP, TM_HOP_ZC, TM_HOP_LDS, TM_HOP_NT (mask: 1 output,
+ * 2 xpay operand, 4 time neighbours) fix one of those choices,
  * TM_XCD_REMAP=0 turns off the XCD-aware block order.                         */
 int tm_set_tuning(tm_ctx *ctx, int enable);
 

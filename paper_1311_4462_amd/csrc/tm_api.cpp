@@ -59,6 +59,7 @@ struct tm_ctx {
     int force_wcap = -1;               // TM_HOP_WCAP: fixed cap of resident waves per SIMD (0: none)
     int force_ldss = -1;               // TM_HOP_LDS: 1 / 0 forces the LDS-staged variant where it exists
     int force_nr = 0;                  // TM_HOP_NR: 1, 2 or 4 rhs per thread where instantiated (0: default)
+    int force_nt = -1;                 // TM_HOP_NT: non-temporal stream mask of the hop launches (see HopCfg)
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
     unsigned lds_per_cu = 0;           // from the runtime at context creation
@@ -272,18 +273,27 @@ struct HopCfg {
     int zc = 0;     // z-planes per brick of the site order (0: lexicographic)
     bool ldss = false;   // x / y neighbours staged in LDS (FP32, one flavour, one rhs)
     int nr = 1;     // right-hand sides per thread
+    // streams accessed non-temporally (HopBatch::nt_streams): 1 output
+    // stores, 2 xpay operand loads, 4 time-neighbour loads.  Streaming the
+    // single-use fields past L2 leaves it to the neighbour spinors that are
+    // re-read; where a launch's output is read back soon from the last-level
+    // cache (working sets within it) ordinary stores do better.
+    int nt = 0;
 };
-// cache code of a tuned configuration
+// cache code of a tuned configuration: block size in bits 0-9, the
+// non-temporal stream mask in bits 10-12
 int cfg_code(const HopCfg &c)
 {
     const int l2nr = c.nr == 4 ? 2 : c.nr == 2 ? 1 : 0;
-    return c.bs | (c.lnt ? 1 << 16 : 0) | (c.ldss ? 1 << 17 : 0) | (l2nr << 18) | (c.wcap << 20) | (c.zc << 24);
+    return c.bs | ((c.nt & 7) << 10) | (c.lnt ? 1 << 16 : 0) | (c.ldss ? 1 << 17 : 0) | (l2nr << 18) |
+           (c.wcap << 20) | (c.zc << 24);
 }
 HopCfg cfg_decode(int code)
 {
-    HopCfg c{code & 0xffff, ((code >> 16) & 1) != 0, (code >> 20) & 0xf, (code >> 24) & 0x7f,
+    HopCfg c{code & 0x3ff, ((code >> 16) & 1) != 0, (code >> 20) & 0xf, (code >> 24) & 0x7f,
              ((code >> 17) & 1) != 0};
     c.nr = 1 << ((code >> 18) & 3);
+    c.nt = (code >> 10) & 7;
     return c;
 }
 // bricks of at most `target` z-planes: the largest divisor of Lz below Lz
@@ -450,7 +460,8 @@ int hop_lds_plan(tm_ctx *ctx, const HopBatch &B, int prec, int nf, int nr, int d
 
 // One launch of the fused hop over up to kMaxProblems problems (same
 // precision, flavour count, recon, dagger, epilogue and rhs grouping).
-int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, HopBatch *B, int zc = 0)
+int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, HopBatch *B, int zc = 0,
+                    int nt = 0)
 {
     const int prec = calls[0].prec, nf = calls[0].g->nf;
     memset(B, 0, sizeof(*B));
@@ -458,6 +469,7 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
     B->gate = ctx->gate;
     B->epi = calls[0].epi;
     B->xcd_remap = ctx->xcd_remap;
+    B->nt_streams = nt;
     int blocks = 0;
     for (int i = 0; i < n; i++) {
         const HopCall &c = calls[i];
@@ -626,7 +638,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             auto trial = [&](const HopCfg &c, int reps, float *ms_per) -> int {
                 HopBatch B;
                 unsigned lds = 0;
-                TM_TRY(build_hop_batch(ctx, tc, n, c.nr, c.bs, &B, c.zc));
+                TM_TRY(build_hop_batch(ctx, tc, n, c.nr, c.bs, &B, c.zc, c.nt));
                 TM_TRY(hop_lds_plan(ctx, B, prec, nf, c.nr, dagger, twl, recon, c, clv, &lds));
                 TM_HIP(ctx, dispatch_hop(B, prec, nf, c.nr, dagger, twl, recon, c, clv, lds, ctx->stream));
                 TM_HIP(ctx, hipEventRecord(e0, ctx->stream));
@@ -646,7 +658,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             for (const HopCfg &c : cand) {
                 HopBatch B;
                 unsigned lds = 0;
-                TM_TRY(build_hop_batch(ctx, tc, n, c.nr, c.bs, &B, c.zc));
+                TM_TRY(build_hop_batch(ctx, tc, n, c.nr, c.bs, &B, c.zc, c.nt));
                 if (hop_lds_plan(ctx, B, prec, nf, c.nr, dagger, twl, recon, c, clv, &lds, true) != TM_OK) continue;
                 float ms;
                 TM_TRY(trial(c, 4, &ms));
@@ -674,6 +686,22 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
                         cfg = c;
                     }
                 }
+            // stage 3: the winner with the single-use streams (output,
+            // xpay operand, time neighbours) loaded / stored non-temporally
+            for (int nt : {3, 7}) {
+                HopCfg c = cfg;
+                c.nt = nt;
+                float ms = 1e30f;
+                for (int rep = 0; rep < 3; rep++) {
+                    float m;
+                    TM_TRY(trial(c, 8, &m));
+                    ms = std::min(ms, m);
+                }
+                if (ms < best) {
+                    best = ms;
+                    cfg = c;
+                }
+            }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             const int code = cfg_code(cfg);
@@ -688,9 +716,10 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
         cfg.ldss = ctx->force_ldss != 0;
     if (cfg.ldss) cfg.zc = 0;
     if (ctx->force_wcap >= 0) cfg.wcap = ctx->force_wcap;
+    if (ctx->force_nt >= 0) cfg.nt = ctx->force_nt;
     HopBatch B;
     unsigned lds = 0;
-    TM_TRY(build_hop_batch(ctx, calls, n, cfg.nr, cfg.bs, &B, cfg.zc));
+    TM_TRY(build_hop_batch(ctx, calls, n, cfg.nr, cfg.bs, &B, cfg.zc, cfg.nt));
     TM_TRY(hop_lds_plan(ctx, B, prec, nf, cfg.nr, dagger, twl, recon, cfg, clv, &lds));
     TM_HIP(ctx, dispatch_hop(B, prec, nf, cfg.nr, dagger, twl, recon, cfg, clv, lds, ctx->stream));
     TM_TRY(finish_reductions(ctx, B.p, n));
@@ -889,6 +918,8 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (e) c->force_ldss = atoi(e) ? 1 : 0;
     e = getenv("TM_HOP_NR");
     if (e) c->force_nr = atoi(e);
+    e = getenv("TM_HOP_NT");
+    if (e) c->force_nt = atoi(e) & 7;
     e = getenv("TM_HOP_WCAP");
     if (e) c->force_wcap = std::min(8, std::max(0, atoi(e)));
     e = getenv("TM_TUNE");

@@ -287,17 +287,19 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
 template <int P, int MU, int SIG, bool BWD>
 __device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
                                          const cx<typename Prec<P>::real> (&u)[3][3], const SpinorPtr &in,
-                                         uint32_t vh, uint32_t vec, uint32_t nb, typename Prec<P>::real sgn)
+                                         uint32_t vh, uint32_t vec, uint32_t nb, typename Prec<P>::real sgn,
+                                         bool tnt = false)
 {
     using real = typename Prec<P>::real;
     real sc;
     if constexpr (P == TM_FP16) {
         uint32_t w[12];
         if constexpr (MU == 3) {
-            if constexpr (SIG > 0)
-                SpinorIO<P>::template load_words<6, 6>(w, in, vh, vec, nb, sc);
+            constexpr int K0 = SIG > 0 ? 6 : 0;
+            if (tnt)
+                SpinorIO<P>::template load_words<K0, 6, true>(w, in, vh, vec, nb, sc);
             else
-                SpinorIO<P>::template load_words<0, 6>(w, in, vh, vec, nb, sc);
+                SpinorIO<P>::template load_words<K0, 6, false>(w, in, vh, vec, nb, sc);
         } else {
             SpinorIO<P>::template load_words<0, 12>(w, in, vh, vec, nb, sc);
         }
@@ -317,10 +319,11 @@ __device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
     } else {
         cx<real> v[12], h[2][3];
         if constexpr (MU == 3) {
-            if constexpr (SIG > 0)
-                SpinorIO<P>::template load_unscaled<6, 6>(v, in, vh, vec, nb, sc);
+            constexpr int K0 = SIG > 0 ? 6 : 0;
+            if (tnt)
+                SpinorIO<P>::template load_unscaled<K0, 6, true>(v, in, vh, vec, nb, sc);
             else
-                SpinorIO<P>::template load_unscaled<0, 6>(v, in, vh, vec, nb, sc);
+                SpinorIO<P>::template load_unscaled<K0, 6, false>(v, in, vh, vec, nb, sc);
         } else {
             SpinorIO<P>::template load_unscaled<0, 12>(v, in, vh, vec, nb, sc);
         }
@@ -377,7 +380,7 @@ template <int P, int NF, int NR, bool DAG, bool TWL, int RECON, bool LNT, int MU
 __device__ __forceinline__ void hop_direction(
     cx<typename Prec<P>::real> (&acc)[NR][flavours_per_thread<NF>()][12], const HopProblem &pb,
     uint32_t nb, uint32_t link_cb, int link_par, int r0, typename Prec<P>::real sgn, int fl,
-    const float4 *lds = nullptr, uint32_t lo = 0, uint32_t span = 0)
+    const float4 *lds = nullptr, uint32_t lo = 0, uint32_t span = 0, int nts = 0)
 {
     using real = typename Prec<P>::real;
     constexpr int SIG = (FWD != DAG) ? 1 : -1;   // D: 1 - g forward; D^+ swaps
@@ -398,7 +401,7 @@ __device__ __forceinline__ void hop_direction(
                 else
                     hop_accumulate<MU, SIG, !FWD>(acc[r][0], u, v, sgn);
             } else {
-                load_hop<P, MU, SIG, !FWD>(acc[r][0], u, pb.in, vh, vec, nb, sgn);
+                load_hop<P, MU, SIG, !FWD>(acc[r][0], u, pb.in, vh, vec, nb, sgn, (nts & kNtTime) != 0);
             }
         }
     } else if constexpr (TWL) {
@@ -438,7 +441,8 @@ __device__ __forceinline__ void hop_direction(
         for (int r = 0; r < NR; r++)
 #pragma unroll
             for (int f = 0; f < NF; f++) {
-                load_hop<P, MU, SIG, !FWD>(acc[r][f], u, pb.in, vh, (uint32_t)((r0 + r) * NF + f), nb, sgn);
+                load_hop<P, MU, SIG, !FWD>(acc[r][f], u, pb.in, vh, (uint32_t)((r0 + r) * NF + f), nb, sgn,
+                                           (nts & kNtTime) != 0);
             }
     }
 }
@@ -498,6 +502,107 @@ constexpr int fence_mode()
     do {                                                 \
         if (fence_mode<P, NF, NR>() == 2) dir_fence(acc); \
     } while (0)
+
+// Epilogue of one output site for the thread's rhs: the twist / xpay of
+// tm_epilogue, the store, and the squared norm of the result for the
+// reduction (added to nrm).
+template <int P, int NF, int NR, bool CLV>
+__device__ __forceinline__ void hop_epilogue(cx<typename Prec<P>::real> (&acc)[NR][flavours_per_thread<NF>()][12],
+                                             const HopProblem &pb, int epi, uint32_t cb, int r0, int fl,
+                                             double (&nrm)[NR], int nts)
+{
+    using real = typename Prec<P>::real;
+    // the xpay operand and the output, non-temporally where nts asks
+    auto load_x = [&](cx<real> *X, uint32_t vec) {
+        if (nts & kNtX)
+            SpinorIO<P>::template load<0, 12, true>(X, pb.x, pb.vh, vec, cb);
+        else
+            SpinorIO<P>::template load<0, 12, false>(X, pb.x, pb.vh, vec, cb);
+    };
+    auto store_out = [&](const cx<real> *A, uint32_t vec) {
+        if (nts & kNtOut)
+            SpinorIO<P>::template store<true>(pb.out, pb.vh, vec, cb, A);
+        else
+            SpinorIO<P>::template store<false>(pb.out, pb.vh, vec, cb, A);
+    };
+    const real kk = (real)pb.k;
+    const uint32_t vh = pb.vh;
+    constexpr bool SPLIT = nd_split<NF>();
+    constexpr int NFT = flavours_per_thread<NF>();
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<real> (&A)[12] = acc[r][0];
+            cx<real> T[12];
+            if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) {
+                twist_split(T, A, pb.tw, true, fl);
+#pragma unroll
+                for (int k = 0; k < 12; k++) A[k] = T[k];
+            }
+            if (epi >= TM_EPI_RX_PLUS_KD) {
+                cx<real> X[12];
+                load_x(X, (uint32_t)((r0 + r) * NF + fl));
+                if (epi == TM_EPI_RX_PLUS_KD) {
+                    twist_split(T, X, pb.tw, false, fl);
+#pragma unroll
+                    for (int k = 0; k < 12; k++) X[k] = T[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 12; k++) A[k] = X[k] + kk * A[k];
+                if (epi == TM_EPI_TWINV_X_PLUS_KD) {
+                    twist_split(T, A, pb.tw, true, fl);
+#pragma unroll
+                    for (int k = 0; k < 12; k++) A[k] = T[k];
+                }
+            }
+            store_out(A, (uint32_t)((r0 + r) * NF + fl));
+            if (pb.red.op != FIN_NONE) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < 12; k++)
+                    s += (double)A[k].re * A[k].re + (double)A[k].im * A[k].im;
+                nrm[r] += s;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<real> (&A)[NFT][12] = acc[r];
+            auto twist = [&](cx<real> (&v)[NF][12], bool inverse) {
+                if constexpr (CLV) {
+                    if constexpr (P == TM_FP64 || P == TM_FP32)
+                        apply_clover<P, NF>(v, pb.clov, vh, cb, pb.tw, inverse);
+                } else {
+                    apply_twist<real, NF>(v, pb.tw, inverse);
+                }
+            };
+            if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) twist(A, true);
+            if (epi >= TM_EPI_RX_PLUS_KD) {
+                cx<real> X[NF][12];
+#pragma unroll
+                for (int f = 0; f < NF; f++)
+                    load_x(X[f], (uint32_t)((r0 + r) * NF + f));
+                if (epi == TM_EPI_RX_PLUS_KD) twist(X, false);
+#pragma unroll
+                for (int f = 0; f < NF; f++)
+#pragma unroll
+                    for (int k = 0; k < 12; k++) A[f][k] = X[f][k] + kk * A[f][k];
+                if (epi == TM_EPI_TWINV_X_PLUS_KD) twist(A, true);
+            }
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                store_out(A[f], (uint32_t)((r0 + r) * NF + f));
+                if (pb.red.op != FIN_NONE) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 12; k++)
+                        s += (double)A[f][k].re * A[f][k].re + (double)A[f][k].im * A[f][k].im;
+                    nrm[r] += s;
+                }
+            }
+        }
+    }
+}
 
 // CLV: twisted clover, the epilogue's twist is the per-site R(x) (clover
 // blocks of the output parity); twist-on-load is not combined with it.
@@ -629,88 +734,13 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
             const uint32_t nb_ = (t == 0) ? cb + (uint32_t)(Lt - 1) * st : cb - st;
             const real sf = (t == Lt - 1) ? (real)pb.tsign : one;
             const real sbk = (t == 0) ? (real)pb.tsign : one;
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, true, LDSS>(acc, pb, nf_, cb, par, r0, sf, fl, st_lds, st_lo, st_span);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, true, LDSS>(acc, pb, nf_, cb, par, r0, sf, fl, st_lds, st_lo, st_span, B.nt_streams);
             TM_HOP_FENCE();
-            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, false, LDSS>(acc, pb, nb_, nb_, npar, r0, sbk, fl, st_lds, st_lo, st_span);
+            hop_direction<P, NF, NR, DAG, TWL, RECON, LNT, 3, false, LDSS>(acc, pb, nb_, nb_, npar, r0, sbk, fl, st_lds, st_lo, st_span, B.nt_streams);
             TM_DIR_FENCE();
         }
 
-        // epilogue
-        const real kk = (real)pb.k;
-        const int epi = B.epi;
-        if constexpr (SPLIT) {
-#pragma unroll
-            for (int r = 0; r < NR; r++) {
-                cx<real> (&A)[12] = acc[r][0];
-                cx<real> T[12];
-                if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) {
-                    twist_split(T, A, pb.tw, true, fl);
-#pragma unroll
-                    for (int k = 0; k < 12; k++) A[k] = T[k];
-                }
-                if (epi >= TM_EPI_RX_PLUS_KD) {
-                    cx<real> X[12];
-                    SpinorIO<P>::template load<0, 12>(X, pb.x, vh, (uint32_t)((r0 + r) * NF + fl), cb);
-                    if (epi == TM_EPI_RX_PLUS_KD) {
-                        twist_split(T, X, pb.tw, false, fl);
-#pragma unroll
-                        for (int k = 0; k < 12; k++) X[k] = T[k];
-                    }
-#pragma unroll
-                    for (int k = 0; k < 12; k++) A[k] = X[k] + kk * A[k];
-                    if (epi == TM_EPI_TWINV_X_PLUS_KD) {
-                        twist_split(T, A, pb.tw, true, fl);
-#pragma unroll
-                        for (int k = 0; k < 12; k++) A[k] = T[k];
-                    }
-                }
-                SpinorIO<P>::store(pb.out, vh, (uint32_t)((r0 + r) * NF + fl), cb, A);
-                if (pb.red.op != FIN_NONE) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int k = 0; k < 12; k++)
-                        s += (double)A[k].re * A[k].re + (double)A[k].im * A[k].im;
-                    nrm[r] += s;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < NR; r++) {
-                cx<real> (&A)[NFT][12] = acc[r];
-                auto twist = [&](cx<real> (&v)[NF][12], bool inverse) {
-                    if constexpr (CLV) {
-                        if constexpr (P == TM_FP64 || P == TM_FP32)
-                            apply_clover<P, NF>(v, pb.clov, vh, cb, pb.tw, inverse);
-                    } else {
-                        apply_twist<real, NF>(v, pb.tw, inverse);
-                    }
-                };
-                if (epi == TM_EPI_TWINV || epi == TM_EPI_X_PLUS_K_TWINV_D) twist(A, true);
-                if (epi >= TM_EPI_RX_PLUS_KD) {
-                    cx<real> X[NF][12];
-#pragma unroll
-                    for (int f = 0; f < NF; f++)
-                        SpinorIO<P>::template load<0, 12>(X[f], pb.x, vh, (uint32_t)((r0 + r) * NF + f), cb);
-                    if (epi == TM_EPI_RX_PLUS_KD) twist(X, false);
-#pragma unroll
-                    for (int f = 0; f < NF; f++)
-#pragma unroll
-                        for (int k = 0; k < 12; k++) A[f][k] = X[f][k] + kk * A[f][k];
-                    if (epi == TM_EPI_TWINV_X_PLUS_KD) twist(A, true);
-                }
-#pragma unroll
-                for (int f = 0; f < NF; f++) {
-                    SpinorIO<P>::store(pb.out, vh, (uint32_t)((r0 + r) * NF + f), cb, A[f]);
-                    if (pb.red.op != FIN_NONE) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int k = 0; k < 12; k++)
-                            s += (double)A[f][k].re * A[f][k].re + (double)A[f][k].im * A[f][k].im;
-                        nrm[r] += s;
-                    }
-                }
-            }
-        }
+        hop_epilogue<P, NF, NR, CLV>(acc, pb, B.epi, cb, r0, fl, nrm, B.nt_streams);
     }
 
     if (pb.red.op != FIN_NONE) {

@@ -139,6 +139,74 @@ __device__ __forceinline__ uint16_t f_to_half(float v)
     if constexpr (P == TM_FP16) return f2h(v); else return f2b(v);
 }
 
+// Non-temporal vector loads (streamed data that is read once per launch).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 ld_nt(const double2 *p)
+{
+    nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_nt(const float4 *p)
+{
+    nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld_nt(const float2 *p)
+{
+    nt_f2 v = __builtin_nontemporal_load((const nt_f2 *)p);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ uint2 ld_nt(const uint2 *p)
+{
+    nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ld_nt(const uint4 *p)
+{
+    nt_u4 v = __builtin_nontemporal_load((const nt_u4 *)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t ld_nt(const uint32_t *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// Non-temporal vector stores (streamed results no kernel of the launch reads).
+__device__ __forceinline__ void st_nt(double2 *p, double2 v)
+{
+    __builtin_nontemporal_store((nt_d2){v.x, v.y}, (nt_d2 *)p);
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 v)
+{
+    __builtin_nontemporal_store((nt_f4){v.x, v.y, v.z, v.w}, (nt_f4 *)p);
+}
+__device__ __forceinline__ void st_nt(uint4 *p, uint4 v)
+{
+    __builtin_nontemporal_store((nt_u4){v.x, v.y, v.z, v.w}, (nt_u4 *)p);
+}
+template <bool NT, typename T>
+__device__ __forceinline__ T lds_(const T *p)
+{
+    if constexpr (NT) return ld_nt(p); else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void sts_(T *p, T v)
+{
+    if constexpr (NT) st_nt(p, v); else *p = v;
+}
+
+// Streams of a hop launch accessed non-temporally (HopBatch::nt_streams):
+// each is touched once per launch, so it need not displace the neighbour
+// spinors that several threads re-read from L2.
+constexpr int kNtOut = 1;     // output stores
+constexpr int kNtX = 2;       // xpay operand loads
+constexpr int kNtTime = 4;    // time-neighbour loads (their other users run a time slice later)
+
 // ------------------------------------------------------------------ spinor access
 //
 // A parity field of nrhs x nf sites-vectors: chunk array + optional scales.
@@ -178,7 +246,7 @@ struct SpinorIO {
 
     // Load complex elements [K0, K0 + N) (multiples of the chunk size) of
     // vector vec = rhs * nf + flavour at site cb.
-    template <int K0, int N>
+    template <int K0, int N, bool NT = false>
     __device__ static __forceinline__ void load(cx<real> *v, const SpinorPtr &s, uint32_t vh,
                                                 uint32_t vec, uint32_t cb)
     {
@@ -186,13 +254,13 @@ struct SpinorIO {
         if constexpr (P == TM_FP64) {
 #pragma unroll
             for (int k = 0; k < N; k++) {
-                double2 c = *at<double2>(row(s, vh, vec, K0 + k), off);
+                double2 c = lds_<NT>(at<double2>(row(s, vh, vec, K0 + k), off));
                 v[k] = mk(c.x, c.y);
             }
         } else if constexpr (P == TM_FP32) {
 #pragma unroll
             for (int k = 0; k < N / 2; k++) {
-                float4 c = *at<float4>(row(s, vh, vec, K0 / 2 + k), off);
+                float4 c = lds_<NT>(at<float4>(row(s, vh, vec, K0 / 2 + k), off));
                 v[2 * k] = mk(c.x, c.y);
                 v[2 * k + 1] = mk(c.z, c.w);
             }
@@ -202,7 +270,7 @@ struct SpinorIO {
             const float sc = *at<float>(s.scale + (size_t)vec * vh, cb * 4u);
             if constexpr (K0 == 0 && N == 12) {
 #pragma unroll
-                for (int k = 0; k < 3; k++) unpack4(v + 4 * k, *at<uint4>(row(s, vh, vec, k), off), sc);
+                for (int k = 0; k < 3; k++) unpack4(v + 4 * k, lds_<NT>(at<uint4>(row(s, vh, vec, k), off)), sc);
             } else if constexpr (K0 == 0 && N == 6) {
                 unpack4(v, *at<uint4>(row(s, vh, vec, 0), off), sc);
                 unpack2(v + 4, *at<uint2>(row(s, vh, vec, 1), off), sc);
@@ -217,12 +285,12 @@ struct SpinorIO {
     // As load, but half-precision values come without the site scale, which
     // is returned in sc (FP32 / FP64: sc = 1), so that a caller that is linear
     // in v applies it once to its result.
-    template <int K0, int N>
+    template <int K0, int N, bool NT = false>
     __device__ static __forceinline__ void load_unscaled(cx<real> *v, const SpinorPtr &s, uint32_t vh,
                                                          uint32_t vec, uint32_t cb, real &sc)
     {
         if constexpr (P == TM_FP64 || P == TM_FP32) {
-            load<K0, N>(v, s, vh, vec, cb);
+            load<K0, N, NT>(v, s, vh, vec, cb);
             sc = (real)1;
         } else {
             const uint32_t off = cb * CB;
@@ -231,19 +299,19 @@ struct SpinorIO {
 #pragma unroll
                 for (int k = 0; k < 3; k++) unpack4(v + 4 * k, *at<uint4>(row(s, vh, vec, k), off), 1.0f);
             } else if constexpr (K0 == 0 && N == 6) {
-                unpack4(v, *at<uint4>(row(s, vh, vec, 0), off), 1.0f);
-                unpack2(v + 4, *at<uint2>(row(s, vh, vec, 1), off), 1.0f);
+                unpack4(v, lds_<NT>(at<uint4>(row(s, vh, vec, 0), off)), 1.0f);
+                unpack2(v + 4, lds_<NT>(at<uint2>(row(s, vh, vec, 1), off)), 1.0f);
             } else {
                 static_assert(K0 == 6 && N == 6, "half-precision loads: full site or one spin pair");
-                unpack2(v, *at<uint2>(row(s, vh, vec, 1), off + 8u), 1.0f);
-                unpack4(v + 2, *at<uint4>(row(s, vh, vec, 2), off), 1.0f);
+                unpack2(v, lds_<NT>(at<uint2>(row(s, vh, vec, 1), off + 8u)), 1.0f);
+                unpack4(v + 2, lds_<NT>(at<uint4>(row(s, vh, vec, 2), off)), 1.0f);
             }
         }
     }
 
     // Half precision: the stored words of complex elements [K0, K0 + N)
     // (real part in the low 16 bits) and the site scale.
-    template <int K0, int N>
+    template <int K0, int N, bool NT = false>
     __device__ static __forceinline__ void load_words(uint32_t *w, const SpinorPtr &s, uint32_t vh,
                                                       uint32_t vec, uint32_t cb, float &sc)
     {
@@ -260,16 +328,16 @@ struct SpinorIO {
 #pragma unroll
             for (int k = 0; k < 3; k++) put4(w + 4 * k, *at<uint4>(row(s, vh, vec, k), off));
         } else if constexpr (K0 == 0 && N == 6) {
-            put4(w, *at<uint4>(row(s, vh, vec, 0), off));
-            const uint2 c = *at<uint2>(row(s, vh, vec, 1), off);
+            put4(w, lds_<NT>(at<uint4>(row(s, vh, vec, 0), off)));
+            const uint2 c = lds_<NT>(at<uint2>(row(s, vh, vec, 1), off));
             w[4] = c.x;
             w[5] = c.y;
         } else {
             static_assert(K0 == 6 && N == 6, "half-precision loads: full site or one spin pair");
-            const uint2 c = *at<uint2>(row(s, vh, vec, 1), off + 8u);
+            const uint2 c = lds_<NT>(at<uint2>(row(s, vh, vec, 1), off + 8u));
             w[0] = c.x;
             w[1] = c.y;
-            put4(w + 2, *at<uint4>(row(s, vh, vec, 2), off));
+            put4(w + 2, lds_<NT>(at<uint4>(row(s, vh, vec, 2), off)));
         }
     }
 
@@ -288,7 +356,8 @@ struct SpinorIO {
         return (uint32_t)f_to_half<P>(a.re * inv) | ((uint32_t)f_to_half<P>(a.im * inv) << 16);
     }
 
-    // Store the full site vector (12 complex).
+    // Store the full site vector (12 complex); NT: non-temporal stores.
+    template <bool NT = false>
     __device__ static __forceinline__ void store(const SpinorPtr &s, uint32_t vh, uint32_t vec,
                                                  uint32_t cb, const cx<real> *v)
     {
@@ -296,12 +365,12 @@ struct SpinorIO {
         if constexpr (P == TM_FP64) {
 #pragma unroll
             for (int k = 0; k < 12; k++)
-                *at_w<double2>((void *)row(s, vh, vec, k), off) = make_double2(v[k].re, v[k].im);
+                sts_<NT>(at_w<double2>((void *)row(s, vh, vec, k), off), make_double2(v[k].re, v[k].im));
         } else if constexpr (P == TM_FP32) {
 #pragma unroll
             for (int k = 0; k < 6; k++)
-                *at_w<float4>((void *)row(s, vh, vec, k), off) =
-                    make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+                sts_<NT>(at_w<float4>((void *)row(s, vh, vec, k), off),
+                         make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
         } else {
             float m = 0.f;
 #pragma unroll
@@ -309,50 +378,13 @@ struct SpinorIO {
             const float inv = (m > 0.f) ? 1.0f / m : 0.f;
 #pragma unroll
             for (int k = 0; k < 3; k++)
-                *at_w<uint4>((void *)row(s, vh, vec, k), off) =
-                    make_uint4(pack1(v[4 * k], inv), pack1(v[4 * k + 1], inv), pack1(v[4 * k + 2], inv),
-                               pack1(v[4 * k + 3], inv));
+                sts_<NT>(at_w<uint4>((void *)row(s, vh, vec, k), off),
+                         make_uint4(pack1(v[4 * k], inv), pack1(v[4 * k + 1], inv), pack1(v[4 * k + 2], inv),
+                                    pack1(v[4 * k + 3], inv)));
             *at_w<float>(s.scale + (size_t)vec * vh, cb * 4u) = m;
         }
     }
 };
-
-// Non-temporal vector loads (streamed data that is read once per launch).
-typedef double nt_d2 __attribute__((ext_vector_type(2)));
-typedef float nt_f4 __attribute__((ext_vector_type(4)));
-typedef float nt_f2 __attribute__((ext_vector_type(2)));
-typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
-typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double2 ld_nt(const double2 *p)
-{
-    nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
-    return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ float4 ld_nt(const float4 *p)
-{
-    nt_f4 v = __builtin_nontemporal_load((const nt_f4 *)p);
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ float2 ld_nt(const float2 *p)
-{
-    nt_f2 v = __builtin_nontemporal_load((const nt_f2 *)p);
-    return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ uint2 ld_nt(const uint2 *p)
-{
-    nt_u2 v = __builtin_nontemporal_load((const nt_u2 *)p);
-    return make_uint2(v.x, v.y);
-}
-__device__ __forceinline__ uint4 ld_nt(const uint4 *p)
-{
-    nt_u4 v = __builtin_nontemporal_load((const nt_u4 *)p);
-    return make_uint4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ uint32_t ld_nt(const uint32_t *p)
-{
-    return __builtin_nontemporal_load(p);
-}
 
 // Link loads: non-temporal (NT) or ordinary.
 template <bool NT, typename T>
@@ -948,6 +980,7 @@ struct HopBatch {
     const int *gate;     // nullable: skip the launch when *gate == 0
     int epi;             // tm_epilogue
     int xcd_remap;       // 1: give every XCD a contiguous range of blocks
+    int nt_streams;      // kNtOut | kNtX | kNtTime: streams accessed non-temporally
     HopProblem p[kMaxProblems];
 };
 

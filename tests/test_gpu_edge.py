@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1311_4462_amd import inputs
-from tests.gpu_util import TOL, from_native, oparams, oracle_dslash, rel, to_native
+from tests.gpu_util import TOL, check_solve, from_native, oparams, oracle_dslash, rel, to_native
 
 pytestmark = pytest.mark.gpu
 
@@ -142,6 +142,46 @@ def test_brick_site_order(api, zc, monkeypatch):
         tx = api.new_field(p, 0)
         r = api.tm_cg(c, tx, to_native(api, c, x, p, 0, 0), g, tol=1e-10, inner=1)[0]
         assert r["status"] == 0 and r["true_rel_res_normal"] <= 1e-10
+        g.close()
+    c.close()
+
+
+@pytest.mark.parametrize("nt", [1, 3, 7])
+def test_non_temporal_streams(api, nt, monkeypatch):
+    """Hop launches that store the output, load the xpay operand and load the
+    time neighbours non-temporally (mask nt): every epilogue and dagger of
+    the hop, all four preconditioned operators in every precision, for one
+    flavour and the doublet, and a mixed solve."""
+    monkeypatch.setenv("TM_HOP_NT", str(nt))
+    c = api.Context()
+    dims = (6, 4, 4, 8)
+    for flavor in (1, 2):
+        p = api.make_params(dims, 0.16, 0.13, 0.17 if flavor == 2 else 0.0, flavor)
+        op = oparams(p)
+        U = inputs.gauge_field(dims, "haar", 131)
+        g = api.Gauge(c, U, p, precs=(0, 1, 2, 3))
+        inp = O.project(inputs.gaussian_spinor(dims, op.nf, 132), dims, 1)
+        xv = O.project(inputs.gaussian_spinor(dims, op.nf, 133), dims, 0)
+        for prec in (0, 1, 2, 3):
+            ti, tx = to_native(api, c, inp, p, prec, 1), to_native(api, c, xv, p, prec, 0)
+            iq, xq = from_native(api, c, ti, p, prec, 1)[0], from_native(api, c, tx, p, prec, 0)[0]
+            out = api.new_field(p, prec)
+            for epi in range(6):
+                for dag in (0, 1):
+                    api.tm_dslash(c, out, ti, g, prec, 0, dag, 0, epi, tx, -0.37)
+                    ref = oracle_dslash(op, U, iq, 0, dag, 0, epi, xq, -0.37)
+                    assert rel(from_native(api, c, out, p, prec, 0)[0], ref) < TOL[prec], (prec, epi, dag)
+            t = to_native(api, c, xv, p, prec, 0)
+            for pc in (0, 1):
+                for dag in (0, 1):
+                    api.tm_mat_pc(c, out, t, g, prec, pc, dag)
+                    ref = O.mat_pc(op, U, xq, "asym" if pc == 0 else "sym", bool(dag))
+                    assert rel(from_native(api, c, out, p, prec, 0)[0], ref) < TOL[prec], (prec, pc, dag)
+        b = to_native(api, c, xv, p, 0, 0)
+        x = api.new_field(p, 0)
+        r = api.tm_cg(c, x, b, g, tol=1e-10, inner=2)[0]
+        assert r["status"] == 0
+        check_solve(op, U, from_native(api, c, x, p, 0, 0)[0], xv, "asym", r["true_rel_res_normal"])
         g.close()
     c.close()
 
