@@ -225,6 +225,25 @@ int tm_dslash(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int pre
 int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, int prec,
               int pc, int dagger, int nrhs);
 
+/* tm_mat_pc for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and launch shapes as tm_mat_pc, with the odd temporary (and,
+ * for the twisted-clover sym^+ form, the twist-on-load temporary) taken from
+ * a 256 MiB device scratch array that every GPU the library runs on holds
+ * from context creation until the process ends.  It allocates nothing and
+ * runs no autotuning (launch shapes already tuned in this context are used,
+ * else the defaults).  Sizes: the temporaries (one odd spinor field of
+ * tm_spinor_bytes(p, prec, nrhs), rounded up to 256 bytes; two for clover
+ * sym^+) must fit in the 256 MiB, else TM_ERR_LIMIT before any launch (the
+ * 32^3 x 64 FP32 doublet needs 192 MiB).  Nothing in the scratch needs to
+ * start at zero: the first kernel writes the whole temporary before the
+ * second reads it.  The scratch is shared by every call on one GPU, from any
+ * context, and keeps the last call's contents: calls that overlap on one GPU
+ * (other streams, other host threads) race.  Errors as tm_mat_pc, plus
+ * TM_ERR_HIP if the scratch's device address could not be resolved.          */
+int tm_mat_pc_noalloc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, int prec,
+                      int pc, int dagger, int nrhs);
+
 /* out = R^-1 in (R^-+ in if dagger) on one parity; inverse = 0 gives R, R^+.
  * The twist is site-local: uniform for twisted mass, the site's clover blocks
  * of that parity for twisted clover.                                          */

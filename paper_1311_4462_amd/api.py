@@ -176,6 +176,11 @@ def tm_mat_pc(ctx, out, inp, gauge: Gauge, prec, pc=ASYM, dagger=0, nrhs=1):
                                      nrhs), "tm_mat_pc")
 
 
+def tm_mat_pc_noalloc(ctx, out, inp, gauge: Gauge, prec, pc=ASYM, dagger=0, nrhs=1):
+    return ctx.check(lib().tm_mat_pc_noalloc(ctx.h, _ptr(out), _ptr(inp), gauge.h, prec, pc, int(dagger),
+                                             nrhs), "tm_mat_pc_noalloc")
+
+
 def tm_twist(ctx, out, inp, gauge: Gauge, prec, parity, dagger=0, inverse=1, nrhs=1):
     return ctx.check(lib().tm_twist(ctx.h, _ptr(out), _ptr(inp), gauge.h, prec, parity,
                                     int(dagger), int(inverse), nrhs), "tm_twist")

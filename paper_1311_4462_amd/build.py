@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libtm.so")
 
 SOURCES = [
     "tm_hop_fp64.hip", "tm_hop_fp32.hip", "tm_hop_fp16.hip", "tm_hop_bf16.hip",
-    "tm_blas.hip", "tm_fields.hip", "tm_force.hip", "tm_clover.hip", "tm_api.cpp",
+    "tm_blas.hip", "tm_fields.hip", "tm_force.hip", "tm_clover.hip", "tm_noalloc.hip", "tm_api.cpp",
 ]
 
 ARCH = os.environ.get("TM_OFFLOAD_ARCH", "gfx950")

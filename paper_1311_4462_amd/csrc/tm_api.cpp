@@ -65,6 +65,14 @@ struct tm_ctx {
     unsigned lds_per_cu = 0;           // from the runtime at context creation
     unsigned lds_per_block = 0;
     std::map<std::string, unsigned> static_lds;   // hop variant -> static LDS bytes
+    // allocation-free calls (tm_mat_pc_noalloc): this device's scratch array
+    // (address resolved at creation), and while such a call runs, the
+    // temporaries it takes from there; no workspace may grow then and the
+    // tuner (which times launches into extra buffers) does not run
+    void *scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
+    bool no_alloc = false;
+    void *tmp_override[2] = {nullptr, nullptr};   // odd temporary, twist-on-load temporary
 };
 
 struct tm_gauge {
@@ -165,6 +173,14 @@ SpinorPtr sptr(const void *p, int prec, uint32_t vh, int nf, int nrhs)
 
 void *workspace(tm_ctx *ctx, const std::string &name, size_t bytes, int *rc)
 {
+    if (ctx->no_alloc) {
+        // an allocation-free call may only use a buffer that is already there
+        auto it = ctx->ws.find(name);
+        if (it != ctx->ws.end() && it->second.ptr && it->second.bytes >= bytes) return it->second.ptr;
+        *rc = fail(ctx, TM_ERR_LIMIT, "allocation-free call: workspace %s of %zu bytes not available",
+                   name.c_str(), bytes);
+        return nullptr;
+    }
     Buf &b = ctx->ws[name];
     if (b.bytes >= bytes && b.ptr) return b.ptr;
     if (b.ptr) {
@@ -203,6 +219,7 @@ double *host_scratch(tm_ctx *ctx, size_t n, int *rc)
 // problem slot and precision.
 void *twl_tmp(tm_ctx *ctx, int slot, const tm_gauge *g, int prec, int nrhs, int *rc)
 {
+    if (ctx->no_alloc && slot == 0 && ctx->tmp_override[1]) return ctx->tmp_override[1];
     char name[64];
     snprintf(name, sizeof(name), "twl_tmp_%d_%d", slot, prec);
     return workspace(ctx, name, spinor_field_bytes(prec, g->vh, g->nf, nrhs), rc);
@@ -610,7 +627,7 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             if (c.bs == want.bs && c.lnt == want.lnt && c.wcap == 0 && c.nr == want.nr) cfg = want;
     } else if (it != ctx->tuned.end()) {
         cfg = cfg_decode(it->second);
-    } else if (ctx->tuning && cand.size() > 1 && !ctx->gate) {
+    } else if (ctx->tuning && cand.size() > 1 && !ctx->gate && !ctx->no_alloc) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(ctx->stream, &cs);
         if (cs == hipStreamCaptureStatusNone) {
@@ -812,6 +829,7 @@ int blas1(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCall &c)
 // Odd temporary of the preconditioned operator, one per problem slot and precision.
 void *odd_tmp(tm_ctx *ctx, int slot, const tm_gauge *g, int prec, int nrhs, int *rc)
 {
+    if (ctx->no_alloc && slot == 0 && ctx->tmp_override[0]) return ctx->tmp_override[0];
     char name[64];
     snprintf(name, sizeof(name), "odd_tmp_%d_%d", slot, prec);
     return workspace(ctx, name, spinor_field_bytes(prec, g->vh, g->nf, nrhs), rc);
@@ -904,6 +922,10 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
         else if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess &&
                  v > 0)
             c->lds_per_block = (unsigned)v;
+        (void)hipGetLastError();
+        // the allocation-free call's scratch on this (the current) device
+        c->scratch_err = noalloc_scratch(c->device, &c->scratch);
+        if (c->scratch_err != hipSuccess) c->scratch = nullptr;
         (void)hipGetLastError();
     }
     const char *e = getenv("TM_XCD_REMAP");
@@ -1125,6 +1147,36 @@ int tm_mat_pc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, int
     if (pc != TM_PC_ASYM && pc != TM_PC_SYM) return fail(ctx, TM_ERR_ARG, "bad pc type");
     if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
     return mat_pc_batch(ctx, &g, &out_e, &in_e, &nrhs, 1, prec, pc, dagger ? 1 : 0, FIN_NONE, nullptr);
+}
+
+int tm_mat_pc_noalloc(tm_ctx *ctx, void *out_e, const void *in_e, const tm_gauge *g, int prec, int pc,
+                      int dagger, int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_gauge_prec(ctx, g, prec));
+    if (!out_e || !in_e) return fail(ctx, TM_ERR_ARG, "null field");
+    if (out_e == in_e) return fail(ctx, TM_ERR_ARG, "out and in must not alias");
+    if (pc != TM_PC_ASYM && pc != TM_PC_SYM) return fail(ctx, TM_ERR_ARG, "bad pc type");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    // the odd temporary, and for the twisted-clover sym^+ form the
+    // twist-on-load temporary, both from the device scratch
+    const size_t field = (spinor_field_bytes(prec, g->vh, g->nf, nrhs) + 255) & ~(size_t)255;
+    const bool twl = g->clover() && pc == TM_PC_SYM && dagger;
+    const size_t need = twl ? 2 * field : field;
+    if (need > kNoAllocScratchBytes)
+        return fail(ctx, TM_ERR_LIMIT,
+                    "tm_mat_pc_noalloc: temporaries of %zu bytes exceed the %zu-byte device scratch", need,
+                    kNoAllocScratchBytes);
+    if (!ctx->scratch)
+        return fail(ctx, TM_ERR_HIP, "tm_mat_pc_noalloc: device scratch unavailable (%s)",
+                    hipGetErrorString(ctx->scratch_err));
+    ctx->tmp_override[0] = ctx->scratch;
+    ctx->tmp_override[1] = twl ? (char *)ctx->scratch + field : nullptr;
+    ctx->no_alloc = true;
+    const int rc = mat_pc_batch(ctx, &g, &out_e, &in_e, &nrhs, 1, prec, pc, dagger ? 1 : 0, FIN_NONE, nullptr);
+    ctx->no_alloc = false;
+    ctx->tmp_override[0] = ctx->tmp_override[1] = nullptr;
+    return rc;
 }
 
 int tm_twist(tm_ctx *ctx, void *out, const void *in, const tm_gauge *g, int prec, int parity,

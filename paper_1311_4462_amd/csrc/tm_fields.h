@@ -16,6 +16,10 @@ hipError_t twist_apply(int prec, int nf, SpinorPtr out, SpinorPtr in, uint32_t v
                        Twist tw, int inverse, hipStream_t st, const void *clov = nullptr,
                        const int *gate = nullptr);
 
+// Device address of the allocation-free call's scratch array on `device`
+// (the current device), resolved once per device and kept.
+hipError_t noalloc_scratch(int device, void **ptr);
+
 // Launch the hop variant selected by the arguments, or, when attr is not
 // null, only fill attr with its function attributes (static LDS, registers).
 template <int P>

@@ -20,6 +20,9 @@ constexpr int kMaxProblems = 8;   // problems per batched launch
 #endif
 constexpr bool kNdSplit = TM_ND_SPLIT != 0;
 constexpr int kBlock = 256;       // default threads per block
+// Device scratch of the allocation-free operator call: 256 MiB per GPU
+// (the odd temporary of the 32^3 x 64 FP32 doublet operator is 192 MiB).
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
 
 // ------------------------------------------------------------------ complex
 
