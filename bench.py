@@ -565,16 +565,16 @@ def main():
     g.close()
     ctx.close()
     del Ut
+    if a.calib_copy:
+        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not a.headline_only:
         extra["deg_24x24x24x48"], U2, b2 = section_24(torch, api, inputs, a)
-        if a.calib_copy:
-            # a plain copy of known size: 256 MiB read + 256 MiB written per launch
-            src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
-            dst = torch.empty_like(src)
-            for _ in range(3):
-                dst.copy_(src)
-            torch.cuda.synchronize()
-            del src, dst
         if not a.no_batch:
             extra["batched"] = batched_section(torch, api, inputs)
             extra.update(force_section(torch, api, inputs))

@@ -170,7 +170,6 @@ __device__ __forceinline__ void mul_accumulate(cx<T> (&acc)[12], const cx<T> (&u
 // The two pairs each product needs, p = (h.re, +-h.im) and s = (h.im, +-h.re),
 // come straight from the stored words, one packed addition each.
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-
 // h = a + k b of two stored words (k = +1, -1, +i, -i for K = 0..3):
 //   p = (h.re, -h.im) if BWD is false, else (h.re, h.im);
 //   s = (h.im, h.re) if BWD is false, else (h.im, -h.re).
@@ -280,6 +279,45 @@ __device__ __forceinline__ void hop_accumulate(cx<T> (&acc)[12], const cx<T> (&u
     mul_accumulate<MU, SIG, BWD>(acc, u, h, sgn);
 }
 
+// binary16 neighbour vec at site nb, hop in direction MU with a link already
+// in packed pairs (u2[a][b] = (re, im) of U_ab): projection, the three
+// two-term dot products per real part, accumulation with the site scale.
+template <int MU, int SIG, bool BWD>
+__device__ __forceinline__ void load_hop_pairs(cx<float> (&acc)[12], const f16x2 (&u2)[3][3], const SpinorPtr &in,
+                                               uint32_t vh, uint32_t vec, uint32_t nb, float sgn, bool tnt)
+{
+    constexpr int P = TM_FP16;
+    float sc;
+    uint32_t w[12];
+    if constexpr (MU == 3) {
+        constexpr int K0 = SIG > 0 ? 6 : 0;
+        if (tnt)
+            SpinorIO<P>::template load_words<K0, 6, true>(w, in, vh, vec, nb, sc);
+        else
+            SpinorIO<P>::template load_words<K0, 6, false>(w, in, vh, vec, nb, sc);
+    } else {
+        SpinorIO<P>::template load_words<0, 12>(w, in, vh, vec, nb, sc);
+    }
+    f16x2 hp[2][3], hs[2][3];
+    project_pairs<MU, SIG, BWD>(hp, hs, w);
+    cx<float> g[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        g[0][c] = link_row_pairs<BWD>(u2, hp[0], hs[0], c);
+        g[1][c] = link_row_pairs<BWD>(u2, hp[1], hs[1], c);
+    }
+    accumulate_hop<MU, SIG>(acc, g, sgn * sc);
+}
+
+// A link as packed binary16 pairs.
+__device__ __forceinline__ void link_pairs(f16x2 (&u2)[3][3], const cx<float> (&u)[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) u2[a][b] = (f16x2){(_Float16)u[a][b].re, (_Float16)u[a][b].im};
+}
+
 // Load the neighbour vector vec at site nb for a hop in direction MU and
 // accumulate it.  The half-precision site scale enters with the hop's factor;
 // binary16 neighbours go through the packed pairs above, the other formats
@@ -293,29 +331,10 @@ __device__ __forceinline__ void load_hop(cx<typename Prec<P>::real> (&acc)[12],
     using real = typename Prec<P>::real;
     real sc;
     if constexpr (P == TM_FP16) {
-        uint32_t w[12];
-        if constexpr (MU == 3) {
-            constexpr int K0 = SIG > 0 ? 6 : 0;
-            if (tnt)
-                SpinorIO<P>::template load_words<K0, 6, true>(w, in, vh, vec, nb, sc);
-            else
-                SpinorIO<P>::template load_words<K0, 6, false>(w, in, vh, vec, nb, sc);
-        } else {
-            SpinorIO<P>::template load_words<0, 12>(w, in, vh, vec, nb, sc);
-        }
-        f16x2 hp[2][3], hs[2][3], u2[3][3];
-        project_pairs<MU, SIG, BWD>(hp, hs, w);
-#pragma unroll
-        for (int a = 0; a < 3; a++)
-#pragma unroll
-            for (int b = 0; b < 3; b++) u2[a][b] = (f16x2){(_Float16)u[a][b].re, (_Float16)u[a][b].im};
-        cx<float> g[2][3];
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            g[0][c] = link_row_pairs<BWD>(u2, hp[0], hs[0], c);
-            g[1][c] = link_row_pairs<BWD>(u2, hp[1], hs[1], c);
-        }
-        accumulate_hop<MU, SIG>(acc, g, sgn * sc);
+        f16x2 u2[3][3];
+        link_pairs(u2, u);
+        load_hop_pairs<MU, SIG, BWD>(acc, u2, in, vh, vec, nb, sgn, tnt);
+        (void)sc;
     } else {
         cx<real> v[12], h[2][3];
         if constexpr (MU == 3) {
@@ -604,6 +623,25 @@ __device__ __forceinline__ void hop_epilogue(cx<typename Prec<P>::real> (&acc)[N
     }
 }
 
+// Site (checkerboard index) of position j of the processing order: j itself
+// (lexicographic), or with z-chunking (pb.zc > 0) the lattice cut into slabs
+// of ts time slices (one XCD's share of the blocks), inside a slab bricks of
+// zc consecutive z-planes of one time slice, all ts slices of a brick column
+// before the next column, so the two time neighbours of a site are read a
+// few planes apart (while they can still be in L2).
+__device__ __forceinline__ uint32_t site_of(const HopProblem &pb, uint32_t j)
+{
+    if (pb.zc <= 0) return j;
+    const uint32_t pl = (uint32_t)(pb.X[0] >> 1) * (uint32_t)pb.X[1];   // sites of an (x, y) plane
+    const uint32_t brick = (uint32_t)pb.zc * pl;
+    const uint32_t column = (uint32_t)pb.ts * brick;                   // ts bricks, one per slice
+    const uint32_t slab = column * (uint32_t)(pb.X[2] / pb.zc);
+    const uint32_t so = j / slab, r1 = j - so * slab;
+    const uint32_t ch = r1 / column, r2 = r1 - ch * column;
+    const uint32_t ti = r2 / brick, r = r2 - ti * brick;
+    return ((so * (uint32_t)pb.ts + ti) * (uint32_t)pb.X[2] + ch * (uint32_t)pb.zc) * pl + r;
+}
+
 // CLV: twisted clover, the epilogue's twist is the per-site R(x) (clover
 // blocks of the output parity); twist-on-load is not combined with it.
 // LDSS: the input spinors of the block's sites and of one y-row either side
@@ -633,12 +671,7 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
     const int grp = lbl - sb * pb.ngrp;
     const int r0 = grp * NR;
     const int fl = SPLIT ? (int)(threadIdx.x & 1) : 0;  // this lane's flavour (split doublet)
-    // j: the site in processing order.  With z-chunking (pb.zc > 0) the
-    // lattice is cut into slabs of ts time slices (one XCD's share of the
-    // blocks); inside a slab the order runs over bricks of zc consecutive
-    // z-planes of one time slice, all ts slices of a brick column before the
-    // next column, so the two time neighbours of a site are read a few planes
-    // apart (while they can still be in L2).
+    // j: the site in processing order (site_of)
     const uint32_t j = (uint32_t)sb * SPB + (SPLIT ? threadIdx.x >> 1 : threadIdx.x);
     const uint32_t vh = pb.vh;
     const bool valid = j < vh;
@@ -661,16 +694,7 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
         }
         __syncthreads();
     }
-    if (pb.zc > 0 && valid) {
-        const uint32_t pl = (uint32_t)(pb.X[0] >> 1) * (uint32_t)pb.X[1];   // sites of an (x, y) plane
-        const uint32_t brick = (uint32_t)pb.zc * pl;
-        const uint32_t column = (uint32_t)pb.ts * brick;                   // ts bricks, one per slice
-        const uint32_t slab = column * (uint32_t)(pb.X[2] / pb.zc);
-        const uint32_t so = j / slab, r1 = j - so * slab;
-        const uint32_t ch = r1 / column, r2 = r1 - ch * column;
-        const uint32_t ti = r2 / brick, r = r2 - ti * brick;
-        cb = ((so * (uint32_t)pb.ts + ti) * (uint32_t)pb.X[2] + ch * (uint32_t)pb.zc) * pl + r;
-    }
+    if (valid) cb = site_of(pb, j);
 
     double nrm[NR];
 #pragma unroll
@@ -815,10 +839,12 @@ __global__ void __launch_bounds__(BS, (hop_waves<P, NF, NR, CLV>())) hop_kernel(
         if constexpr (P == TM_FP64 || P == TM_FP32) {                                          \
             TM_HOP_CASES_CLV(P, 1, 12, 256)                                                    \
             TM_HOP_CASES_CLV(P, 1, 12, 64)                                                     \
-            TM_HOP_CASES_CLV(P, 2, 12, 256)                                                    \
-            TM_HOP_CASES_CLV(P, 2, 12, 64)                                                     \
             TM_HOP_CASES_CLV(P, 1, 18, 256)                                                    \
-            TM_HOP_CASES_CLV(P, 2, 18, 256)                                                    \
+            if constexpr (!kNdSplit) {                                                         \
+                TM_HOP_CASES_CLV(P, 2, 12, 256)                                                \
+                TM_HOP_CASES_CLV(P, 2, 12, 64)                                                 \
+                TM_HOP_CASES_CLV(P, 2, 18, 256)                                                \
+            }                                                                                  \
         }                                                                                      \
         TM_HOP_CASES(P, 1, 1, 12, 256)                                                         \
         TM_HOP_CASES(P, 1, 1, 12, 128)                                                         \
