@@ -308,6 +308,11 @@ int tm_dot(tm_ctx *ctx, double *out_host /* 2*nrhs: re, im */, const void *x, co
 /* dst = src converted between precisions (same parity, nrhs).                 */
 int tm_convert(tm_ctx *ctx, void *dst, int dst_prec, const void *src, int src_prec,
                const tm_params *p, int nrhs);
+/* dst = a src, converted between precisions as tm_convert (dst may be src
+ * when the precisions agree); a must be finite.  Used for the chain rule of
+ * the action's gradient with respect to the source (2 dS/dS_out X).          */
+int tm_scale(tm_ctx *ctx, void *dst, int dst_prec, const void *src, int src_prec, double a,
+             const tm_params *p, int nrhs);
 
 /* Gauge force for S = phi^+ (M^+ M)^-1 phi with M the asymmetric (or
  * symmetric) preconditioned operator and X = (M^+ M)^-1 phi given (even,

@@ -62,6 +62,7 @@ _SIGS = {
                           c_int, c_void_p, c_double, c_int]),
     "tm_mat_pc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
     "tm_mat_pc_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
+    "tm_scale": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, c_double, P(tm_params), c_int]),
     "tm_twist": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "tm_twist_inv": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
     "tm_prepare": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int]),

@@ -287,6 +287,11 @@ def tm_convert(ctx, dst, dst_prec, src, src_prec, params: tm_params, nrhs=1):
                                       ctypes.byref(params), nrhs), "tm_convert")
 
 
+def tm_scale(ctx, dst, dst_prec, src, src_prec, a, params: tm_params, nrhs=1):
+    return ctx.check(lib().tm_scale(ctx.h, _ptr(dst), dst_prec, _ptr(src), src_prec, float(a),
+                                    ctypes.byref(params), nrhs), "tm_scale")
+
+
 def tm_force(ctx, F, force_prec, X_e, gauge: Gauge, prec, pc=ASYM, coeff=1.0, accumulate=False,
              G=None):
     return ctx.check(lib().tm_force(ctx.h, _ptr(F), force_prec, _ptr(X_e), gauge.h, prec, pc,

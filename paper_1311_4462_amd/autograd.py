@@ -6,7 +6,9 @@ on the GPU) and phi a canonical source whose even sites are used.  Forward runs
 the library's FP64 CG; backward recomputes the solve (nothing but U and phi is
 stored) and calls the hand-written force kernel (tm_force), which returns the
 unconstrained gradient G with dS = Re tr(G^+ dU) -- torch's convention for a
-real function of complex inputs -- and grad_phi = 2 X.
+real function of complex inputs -- and grad_phi = 2 X.  The incoming gradient
+enters as the force kernel's coefficient and as the factor of tm_scale, so the
+binding only moves data (packing, dtype of the returned tensors).
 """
 from __future__ import annotations
 
@@ -64,12 +66,14 @@ class TMAction(torch.autograd.Function):
             fdt = torch.complex64
         F = torch.empty(U.shape, dtype=fdt, device=U.device)
         G = torch.empty(U.shape, dtype=fdt, device=U.device)
-        api.tm_force(ctx, F, force_prec, xf, g, force_prec, pc, 1.0, False, G)
-        gU = G.to(torch.complex128) * gS
+        gs = float(gS)
+        api.tm_force(ctx, F, force_prec, xf, g, force_prec, pc, gs, False, G)
+        gU = G.to(torch.complex128)
         gphi = None
         if fctx.needs_input_grad[1]:
+            api.tm_scale(ctx, x, api.FP64, x, api.FP64, 2.0 * gs, params)
             X = api.tm_spinor_unpack(ctx, x, params, api.FP64, 0)[0]
-            gphi = (2.0 * gS) * X.reshape(phi.shape).to(phi.dtype)
+            gphi = X.reshape(phi.shape).to(phi.dtype)
         g.close()
         return gU, gphi, None, None, None, None, None
 

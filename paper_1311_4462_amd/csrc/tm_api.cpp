@@ -762,13 +762,15 @@ struct BlasCall {
     double *red_out;
 };
 
-int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCall *calls, int n)
+int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCall *calls, int n,
+                      double scale = 1.0)
 {
     if (n < 1 || n > kMaxProblems) return fail(ctx, TM_ERR_LIMIT, "too many problems in a batch");
     BlasBatch B;
     memset(&B, 0, sizeof(B));
     B.nprob = n;
     B.nf = nf;
+    B.scale = scale;
     B.gate = ctx->gate;
     int blocks = 0;
     for (int i = 0; i < n; i++) {
@@ -819,9 +821,9 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
     return TM_OK;
 }
 
-int blas1(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCall &c)
+int blas1(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCall &c, double scale = 1.0)
 {
-    return launch_blas_batch(ctx, op, pa, pb, nf, &c, 1);
+    return launch_blas_batch(ctx, op, pa, pb, nf, &c, 1, scale);
 }
 
 // ------------------------------------------------------------------ operators
@@ -1274,6 +1276,19 @@ int tm_convert(tm_ctx *ctx, void *dst, int dst_prec, const void *src, int src_pr
     if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
     BlasCall c{half_volume(*p), nrhs, {src, dst, nullptr, nullptr}, FIN_NONE, nullptr, nullptr};
     return blas1(ctx, OP_CONVERT, src_prec, dst_prec, nflav(*p), c);
+}
+
+int tm_scale(tm_ctx *ctx, void *dst, int dst_prec, const void *src, int src_prec, double a, const tm_params *p,
+             int nrhs)
+{
+    if (!ctx) return TM_ERR_ARG;
+    TM_TRY(check_params(ctx, p));
+    if (!dst || !src) return fail(ctx, TM_ERR_ARG, "null field");
+    if (!valid_prec(dst_prec) || !valid_prec(src_prec)) return fail(ctx, TM_ERR_PREC, "bad precision");
+    if (nrhs < 1) return fail(ctx, TM_ERR_ARG, "nrhs must be >= 1");
+    if (!std::isfinite(a)) return fail(ctx, TM_ERR_ARG, "non-finite factor");
+    BlasCall c{half_volume(*p), nrhs, {src, dst, nullptr, nullptr}, FIN_NONE, nullptr, nullptr};
+    return blas1(ctx, OP_CONVERT, src_prec, dst_prec, nflav(*p), c, a);
 }
 
 // ------------------------------------------------------------------ CG

@@ -191,6 +191,8 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                     unit_store<PB, U>(pb.v[2], rb, u, cb, vh, a0[q]);
                     if (pb.v[3].data) unit_store<PB, U>(pb.v[3], rb, u, cb, vh, a0[q]);
                 } else if constexpr (OP == OP_CONVERT) {
+#pragma unroll
+                    for (int k = 0; k < U; k++) a0[q][k] = B.scale * a0[q][k];
                     unit_store<PB, U>(pb.v[1], rb, u, cb, vh, a0[q]);
                 } else if constexpr (OP == OP_ACCUM_ZERO) {  // y += x, x = 0
 #pragma unroll
@@ -252,6 +254,8 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
             } else if constexpr (OP == OP_CONVERT) {
                 cx<double> a[12];
                 load_d<PA>(a, pb.v[0], vh, vec, cb);
+#pragma unroll
+                for (int k = 0; k < 12; k++) a[k] = B.scale * a[k];
                 store_d<PB>(pb.v[1], vh, vec, cb, a);
             } else if constexpr (OP == OP_ACCUM_ZERO) {
                 cx<double> y[12], x[12];

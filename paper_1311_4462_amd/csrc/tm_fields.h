@@ -36,7 +36,7 @@ enum BlasOp {
     OP_CG_UPDATE = 0,   // v0 (PA) += alpha v1; v2 -= alpha v3; |v2|^2        (v1..v3: PB)
     OP_XPAY = 1,        // v1 = v0 + beta v1                                  (PB)
     OP_RESIDUAL = 2,    // v2 (PB) = v0 - v1 (PA; v1 null: 0); v3 (PB, optional) = v2; |v2|^2
-    OP_CONVERT = 3,     // v1 (PB) = v0 (PA)
+    OP_CONVERT = 3,     // v1 (PB) = scale v0 (PA)
     OP_ACCUM_ZERO = 4,  // v0 (PA) += v1 (PB); v1 = 0
     OP_NORM2 = 5,       // |v0|^2 (PA)
     OP_DOT = 6          // <v0, v1> (PA), re / im
@@ -55,6 +55,7 @@ struct BlasBatch {
     int nprob;
     int total_blocks;
     int nf;
+    double scale;        // OP_CONVERT's factor (1: a plain conversion)
     const int *gate;     // nullable: skip the launch when *gate == 0
     BlasProblem p[kMaxProblems];
 };

@@ -222,6 +222,52 @@ def test_lds_staged_neighbours(api, monkeypatch):
     c.close()
 
 
+def test_lds_staged_neighbours_several_rhs(api, monkeypatch):
+    """The LDS-staged variant with several rhs (one per thread, each block
+    staging its own rhs) and several lattices in one launch: every epilogue
+    and dagger on every rhs, and a batched mixed solve over uneven lattices."""
+    monkeypatch.setenv("TM_HOP_LDS", "1")
+    monkeypatch.setenv("TM_HOP_NR", "1")
+    c = api.Context()
+    nrhs = 3
+    dims = (8, 6, 4, 10)
+    p = api.make_params(dims, 0.16, 0.13, 0.0, 1)
+    op = oparams(p)
+    U = inputs.gauge_field(dims, "haar", 171)
+    g = api.Gauge(c, U, p, precs=(0, 1))
+    inp = O.project(inputs.gaussian_spinor(dims, 1, 172, nrhs=nrhs), dims, 1)
+    xv = O.project(inputs.gaussian_spinor(dims, 1, 173, nrhs=nrhs), dims, 0)
+    ti, tx = to_native(api, c, inp, p, 1, 1, nrhs), to_native(api, c, xv, p, 1, 0, nrhs)
+    out = api.new_field(p, 1, nrhs)
+    for epi in range(6):
+        for dag in (0, 1):
+            api.tm_dslash(c, out, ti, g, 1, 0, dag, 0, epi, tx, -0.37, nrhs=nrhs)
+            got = from_native(api, c, out, p, 1, 0, nrhs)
+            for r in range(nrhs):
+                ref = oracle_dslash(op, U, inp[r], 0, dag, 0, epi, xv[r], -0.37)
+                assert rel(got[r], ref) < TOL[1], (epi, dag, r)
+    g.close()
+    probs = []
+    for i, d in enumerate(((4, 4, 4, 4), (6, 4, 2, 8), (8, 6, 4, 10))):
+        pi = api.make_params(d, 0.15, 0.1, 0.0, 1)
+        Ui = inputs.gauge_field(d, "haar", 180 + i)
+        gi = api.Gauge(c, Ui, pi, precs=(0, 1))
+        bi = O.project(inputs.gaussian_spinor(d, 1, 190 + i, nrhs=nrhs), d, 0)
+        probs.append((pi, Ui, gi, bi, to_native(api, c, bi, pi, 0, 0, nrhs), api.new_field(pi, 0, nrhs)))
+    for gk in (0, 8):
+        res = api.tm_cg_batched(c, [q[2] for q in probs], [q[5] for q in probs], [q[4] for q in probs],
+                                [nrhs] * len(probs), tol=1e-10, inner=1, graph_iters=gk)
+        for k, (pi, Ui, gi, bi, tbi, xi) in enumerate(probs):
+            xs = from_native(api, c, xi, pi, 0, 0, nrhs)
+            for r in range(nrhs):
+                rr = res[k * nrhs + r]
+                assert rr["status"] == 0, (gk, k, r, rr)
+                check_solve(oparams(pi), Ui, xs[r], bi[r], "asym", rr["true_rel_res_normal"])
+    for q in probs:
+        q[2].close()
+    c.close()
+
+
 @pytest.mark.parametrize("nr", [1, 2, 4])
 def test_rhs_per_thread(api, nr, monkeypatch):
     """Each grouping of right-hand sides per thread (1, 2 or 4; FP64 at most

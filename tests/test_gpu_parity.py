@@ -213,6 +213,17 @@ def test_blas_norm_dot(api, ctx):
         back = api.new_field(p, 0, 3)
         api.tm_convert(ctx, back, 0, t, prec, p, 3)
         assert rel(from_native(api, ctx, back, p, 0, 1, 3), a) < {1: 1e-7, 2: 1e-3, 3: 5e-3}[prec]
+    # dst = a src: in place in FP64 (exact scaling by a power of two, then a
+    # general factor), and converted into every precision
+    t = to_native(api, ctx, a, p, 0, 1, 3)
+    api.tm_scale(ctx, t, 0, t, 0, -0.5, p, 3)
+    assert np.array_equal(from_native(api, ctx, t, p, 0, 1, 3), -0.5 * a)
+    api.tm_scale(ctx, t, 0, t, 0, 2.37, p, 3)
+    assert rel(from_native(api, ctx, t, p, 0, 1, 3), -1.185 * a) < 1e-15
+    for prec in (1, 2, 3):
+        t = api.new_field(p, prec, 3)
+        api.tm_scale(ctx, t, prec, ta, 0, -1.7, p, 3)
+        assert rel(from_native(api, ctx, t, p, prec, 1, 3), -1.7 * a) < {1: 1e-7, 2: 1e-3, 3: 5e-3}[prec]
 
 
 # ------------------------------------------------------------------ solvers
