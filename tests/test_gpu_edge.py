@@ -268,6 +268,74 @@ def test_lds_staged_neighbours_several_rhs(api, monkeypatch):
     c.close()
 
 
+SHAPES = [
+    # forced launch choices (TM_HOP_*), each combined with several rhs
+    {"NR": "2", "ZC": "2", "NT": "7"},
+    {"NR": "4", "ZC": "4", "NT": "3", "WCAP": "2"},
+    {"NR": "1", "LDS": "1", "NT": "1"},
+    {"NR": "1", "BS": "64", "ZC": "2", "NT": "7", "WCAP": "3"},
+    {"NR": "2", "BS": "128", "LINK": "0", "NT": "3"},
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda d: ",".join(f"{k}{v}" for k, v in d.items()))
+def test_launch_shapes_several_rhs(api, shape, monkeypatch):
+    """Combinations of tuner choices on launches with several rhs: every
+    epilogue and dagger of the hop on every rhs against the oracle (FP32 and
+    FP16), and a batched mixed solve over two uneven lattices that must take
+    as many iterations as with the default launch shapes (a wrong inner
+    operator can still converge through the FP64 reliable updates, only
+    more slowly)."""
+    nrhs = 4
+    probs_dims = ((6, 4, 4, 8), (4, 6, 2, 6))
+
+    def batched_solve(c):
+        probs = []
+        for i, d in enumerate(probs_dims):
+            pi = api.make_params(d, 0.15, 0.1, 0.0, 1)
+            Ui = inputs.gauge_field(d, "haar", 210 + i)
+            gi = api.Gauge(c, Ui, pi, precs=(0, 1))
+            bi = O.project(inputs.gaussian_spinor(d, 1, 220 + i, nrhs=nrhs), d, 0)
+            probs.append((pi, Ui, gi, bi, to_native(api, c, bi, pi, 0, 0, nrhs), api.new_field(pi, 0, nrhs)))
+        res = api.tm_cg_batched(c, [q[2] for q in probs], [q[5] for q in probs], [q[4] for q in probs],
+                                [nrhs] * len(probs), tol=1e-10, inner=1)
+        for k, (pi, Ui, gi, bi, tbi, xi) in enumerate(probs):
+            xs = from_native(api, c, xi, pi, 0, 0, nrhs)
+            for r in range(nrhs):
+                assert res[k * nrhs + r]["status"] == 0
+                check_solve(oparams(pi), Ui, xs[r], bi[r], "asym", res[k * nrhs + r]["true_rel_res_normal"])
+            gi.close()
+        return res[0]["iters"]
+
+    c0 = api.Context()
+    iters_default = batched_solve(c0)
+    c0.close()
+    for k, v in shape.items():
+        monkeypatch.setenv("TM_LINK_NT" if k == "LINK" else "TM_HOP_" + k, v)
+    c = api.Context()
+    dims = (8, 6, 4, 10)
+    p = api.make_params(dims, 0.16, 0.13, 0.0, 1)
+    op = oparams(p)
+    U = inputs.gauge_field(dims, "haar", 201)
+    g = api.Gauge(c, U, p, precs=(0, 1, 2))
+    inp = O.project(inputs.gaussian_spinor(dims, 1, 202, nrhs=nrhs), dims, 1)
+    xv = O.project(inputs.gaussian_spinor(dims, 1, 203, nrhs=nrhs), dims, 0)
+    for prec in (1, 2):
+        ti, tx = to_native(api, c, inp, p, prec, 1, nrhs), to_native(api, c, xv, p, prec, 0, nrhs)
+        iq, xq = from_native(api, c, ti, p, prec, 1, nrhs), from_native(api, c, tx, p, prec, 0, nrhs)
+        out = api.new_field(p, prec, nrhs)
+        for epi in range(6):
+            for dag in (0, 1):
+                api.tm_dslash(c, out, ti, g, prec, 0, dag, 0, epi, tx, -0.37, nrhs=nrhs)
+                got = from_native(api, c, out, p, prec, 0, nrhs)
+                for r in range(nrhs):
+                    ref = oracle_dslash(op, U, iq[r], 0, dag, 0, epi, xq[r], -0.37)
+                    assert rel(got[r], ref) < TOL[prec], (prec, epi, dag, r)
+    g.close()
+    assert batched_solve(c) <= iters_default + 2
+    c.close()
+
+
 @pytest.mark.parametrize("nr", [1, 2, 4])
 def test_rhs_per_thread(api, nr, monkeypatch):
     """Each grouping of right-hand sides per thread (1, 2 or 4; FP64 at most
