@@ -332,6 +332,24 @@ def test_launch_shapes_several_rhs(api, shape, monkeypatch):
                     ref = oracle_dslash(op, U, iq[r], 0, dag, 0, epi, xq[r], -0.37)
                     assert rel(got[r], ref) < TOL[prec], (prec, epi, dag, r)
     g.close()
+    # the doublet (one rhs per thread; the other choices apply) with two rhs
+    pd = api.make_params(dims, 0.16, 0.13, 0.17, 2)
+    opd = oparams(pd)
+    gd = api.Gauge(c, U, pd, precs=(0, 1, 2))
+    ind = O.project(inputs.gaussian_spinor(dims, 2, 204, nrhs=2), dims, 1)
+    xd = O.project(inputs.gaussian_spinor(dims, 2, 205, nrhs=2), dims, 0)
+    for prec in (0, 1, 2):
+        ti, tx = to_native(api, c, ind, pd, prec, 1, 2), to_native(api, c, xd, pd, prec, 0, 2)
+        iq, xq = from_native(api, c, ti, pd, prec, 1, 2), from_native(api, c, tx, pd, prec, 0, 2)
+        out = api.new_field(pd, prec, 2)
+        for epi in (1, 2, 4):
+            for dag in (0, 1):
+                api.tm_dslash(c, out, ti, gd, prec, 0, dag, 0, epi, tx, -0.37, nrhs=2)
+                got = from_native(api, c, out, pd, prec, 0, 2)
+                for r in range(2):
+                    ref = oracle_dslash(opd, U, iq[r], 0, dag, 0, epi, xq[r], -0.37)
+                    assert rel(got[r], ref) < TOL[prec], ("doublet", prec, epi, dag, r)
+    gd.close()
     assert batched_solve(c) <= iters_default + 2
     c.close()
 
