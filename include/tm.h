@@ -329,8 +329,9 @@ int tm_force(tm_ctx *ctx, void *F_dev, int force_prec, const void *X_e, const tm
  * divide every problem's count; one flavour, 12-real links), block size,
  * link-load policy, cap of resident waves per SIMD, LDS staging (FP32 one
  * flavour), then the four fastest of those in each depth of the brick site
- * order, then the winner with its single-use streams (output stores, xpay
- * operand and time-neighbour loads) accessed non-temporally -- cached per
+ * order, then the three best of those with their single-use streams (output
+ * stores; with the xpay operand and / or the time-neighbour loads) accessed
+ * non-temporally -- cached per
  * context and persisted to $TM_TUNE_CACHE if set; 0 disables (defaults are
  * then used).
  * Read at context creation, for experiments: TM_HOP_NR, TM_HOP_BS,

@@ -687,38 +687,45 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             // lexicographic order), timed longer: the best of three batches
             // of eight launches, which is less sensitive to clock changes
             float best = 1e30f;
+            auto timed = [&](const HopCfg &c, float *ms) -> int {
+                *ms = 1e30f;
+                for (int rep = 0; rep < 3; rep++) {
+                    float m;
+                    TM_TRY(trial(c, 8, &m));
+                    *ms = std::min(*ms, m);
+                }
+                return TM_OK;
+            };
+            std::vector<std::pair<float, HopCfg>> t2;
             for (size_t i = 0; i < std::min<size_t>(4, t1.size()); i++)
                 for (int z : {0, 8, 4, 2}) {
                     HopCfg c = t1[i].second;
                     if (z && c.ldss) break;
                     c.zc = z;
-                    float ms = 1e30f;
-                    for (int rep = 0; rep < 3; rep++) {
-                        float m;
-                        TM_TRY(trial(c, 8, &m));
-                        ms = std::min(ms, m);
-                    }
+                    float ms;
+                    TM_TRY(timed(c, &ms));
+                    t2.push_back({ms, c});
                     if (ms < best) {
                         best = ms;
                         cfg = c;
                     }
                 }
-            // stage 3: the winner with the single-use streams (output,
-            // xpay operand, time neighbours) loaded / stored non-temporally
-            for (int nt : {3, 7}) {
-                HopCfg c = cfg;
-                c.nt = nt;
-                float ms = 1e30f;
-                for (int rep = 0; rep < 3; rep++) {
-                    float m;
-                    TM_TRY(trial(c, 8, &m));
-                    ms = std::min(ms, m);
+            // stage 3: the three best of stage 2 with the single-use streams
+            // non-temporal (output; with the xpay operand and / or the time
+            // neighbours): which helps depends on the site order and on the
+            // block shape, so they are tried together
+            std::sort(t2.begin(), t2.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+            for (size_t i = 0; i < std::min<size_t>(3, t2.size()); i++)
+                for (int nt : {1, 3, 5, 7}) {
+                    HopCfg c = t2[i].second;
+                    c.nt = nt;
+                    float ms;
+                    TM_TRY(timed(c, &ms));
+                    if (ms < best) {
+                        best = ms;
+                        cfg = c;
+                    }
                 }
-                if (ms < best) {
-                    best = ms;
-                    cfg = c;
-                }
-            }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             const int code = cfg_code(cfg);
