@@ -521,6 +521,13 @@ def main():
     Ut = torch.from_numpy(U3).cuda()
     precs = (api.FP32,) if a.headline_only else (api.FP64, api.FP32, api.FP16, api.BF16)
     g = api.Gauge(ctx, Ut, p, recon=12, precs=precs)
+    if a.cg_only:
+        # profiling mode: the CG comparison alone, its results as one JSON line
+        out = cg_comparison(torch, api, ctx, g, p, inputs, a.cg_reps)
+        g.close()
+        ctx.close()
+        print(json.dumps({"cg_32x32x32x64_nd": out}), flush=True)
+        return
     h = headline(torch, api, ctx, g, p, a)
     vh = h["vh"]
     value = FLOPS_PER_SITE["nd"] * vh / h["dt"] / 1e9
