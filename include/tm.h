@@ -127,7 +127,7 @@ typedef struct {
     int maxiter;          /* iteration cap (inner iterations for mixed)         */
     int outer;            /* precision of x and b: TM_FP64                      */
     int inner;            /* TM_FP64 (plain CG) or TM_FP32 / FP16 / BF16 (mixed) */
-    double delta;         /* reliable-update threshold (mixed); 0: 0.01 (FP16/BF16), 0.001 (FP32);
+    double delta;         /* reliable-update threshold (mixed); 0: 0.01 (FP16), 0.02 (BF16), 0.001 (FP32);
                              raised to 2e-3 (FP16), 1e-2 (BF16), 1e-5 (FP32) at least */
     int use_x0;           /* 1: x holds the initial guess                       */
     int nrhs;             /* right-hand sides solved together (>= 1)            */

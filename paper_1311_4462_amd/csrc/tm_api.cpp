@@ -1465,14 +1465,18 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     const int pc = par->pc;
     const int inner = par->inner;
     const bool mixed = inner != TM_FP64;
-    // reliable-update threshold: by default 0.01 for half-precision inner
-    // iterations and 0.001 for FP32 (the residual is replaced once it has
-    // dropped by 1/delta since the last replacement)
+    // reliable-update threshold: by default 0.01 for FP16 inner iterations,
+    // 0.02 for BF16 (its 8-bit mantissa lets the iterated residual drift from
+    // the true one sooner: on the 32^3 x 64 doublet 50 iterations and 6
+    // updates at 0.02 against 61 and 5 at 0.01) and 0.001 for FP32 (the
+    // residual is replaced once it has dropped by 1/delta since the last
+    // replacement)
     // Below a floor set by the inner format's precision the iterated residual
     // stagnates before it has dropped by delta and no update would come
     // (measured: BF16 at 0.002 never converges), so delta is raised to it.
     const double delta_floor = inner == TM_FP32 ? 1e-5 : (inner == TM_FP16 ? 2e-3 : 1e-2);
-    const double delta = std::max(par->delta > 0 ? par->delta : (inner == TM_FP32 ? 1e-3 : 1e-2), delta_floor);
+    const double delta_default = inner == TM_FP32 ? 1e-3 : (inner == TM_FP16 ? 1e-2 : 2e-2);
+    const double delta = std::max(par->delta > 0 ? par->delta : delta_default, delta_floor);
     const int check_every = par->check_every > 0 ? par->check_every : 8;
     const int nf = pr[0].g->nf;
 
