@@ -60,6 +60,7 @@ struct tm_ctx {
     int force_ldss = -1;               // TM_HOP_LDS: 1 / 0 forces the LDS-staged variant where it exists
     int force_nr = 0;                  // TM_HOP_NR: 1, 2 or 4 rhs per thread where instantiated (0: default)
     int force_nt = -1;                 // TM_HOP_NT: non-temporal stream mask of the hop launches (see HopCfg)
+    int cg_fuse = 1;                   // TM_CG_FUSE=0: CG residual update as a separate BLAS pass
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
     unsigned lds_per_cu = 0;           // from the runtime at context creation
@@ -258,6 +259,7 @@ struct HopCall {
     int fin;                 // FinOp for |out|^2 (FIN_NONE: no reduction)
     CGScalars *cg;
     double *red_out;
+    int upd = 0;             // CG residual update: out -= alpha (epilogue result), alpha from cg
 };
 
 #ifndef TM_FP64_NR
@@ -519,6 +521,8 @@ int build_hop_batch(tm_ctx *ctx, const HopCall *calls, int n, int nr, int bs, Ho
         hp.in = sptr(c.in, prec, g->vh, nf, c.nrhs);
         hp.out = sptr(c.out, prec, g->vh, nf, c.nrhs);
         hp.x = c.x ? sptr(c.x, prec, g->vh, nf, c.nrhs) : SpinorPtr{nullptr, nullptr};
+        if (c.upd && !c.cg) return fail(ctx, TM_ERR_ARG, "internal: residual update needs CG scalars");
+        hp.upd = c.upd ? c.cg : nullptr;
         hp.red.op = c.fin;
         if ((c.fin == FIN_ALPHA || c.fin == FIN_BETA || c.fin == FIN_STORE_RR || c.fin == FIN_RELIABLE) && !c.cg)
             return fail(ctx, TM_ERR_ARG, "internal: hop reduction needs CG scalars");
@@ -636,11 +640,12 @@ int launch_hops(tm_ctx *ctx, const HopCall *calls, int n)
             // lexicographic site order, then the four best of those with each
             // brick depth of the site order.  Trials write a scratch output
             // wherever a call's output is also one of its inputs (an in-place
-            // xpay would otherwise accumulate over the repeated launches).
+            // xpay or a residual update would otherwise accumulate over the
+            // repeated launches).
             HopCall tc[kMaxProblems];
             for (int i = 0; i < n; i++) {
                 tc[i] = calls[i];
-                if (tc[i].out == tc[i].x || tc[i].out == tc[i].in) {
+                if (tc[i].out == tc[i].x || tc[i].out == tc[i].in || tc[i].upd) {
                     char name[48];
                     snprintf(name, sizeof(name), "tune_out_%d", i);
                     int rc = TM_OK;
@@ -796,6 +801,7 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         int vp[4] = {pa, pa, pa, pa};
         switch (op) {
         case OP_CG_UPDATE: vp[1] = vp[2] = vp[3] = pb; break;
+        case OP_X_UPDATE: vp[1] = pb; break;
         case OP_XPAY: vp[0] = vp[1] = pb; break;
         case OP_RESIDUAL: vp[2] = vp[3] = pb; break;
         case OP_CONVERT: vp[1] = pb; break;
@@ -807,7 +813,7 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         bp.red.op = c.fin;
         bp.red.cg = c.cg;
         // the CG update reads alpha and the xpay reads beta from the scalars
-        if ((op == OP_CG_UPDATE || op == OP_XPAY || c.fin == FIN_ALPHA || c.fin == FIN_BETA ||
+        if ((op == OP_CG_UPDATE || op == OP_X_UPDATE || op == OP_XPAY || c.fin == FIN_ALPHA || c.fin == FIN_BETA ||
              c.fin == FIN_STORE_RR || c.fin == FIN_RELIABLE) && !c.cg)
             return fail(ctx, TM_ERR_ARG, "internal: BLAS op %d needs CG scalars", op);
         if (c.fin == FIN_STORE && !c.red_out) return fail(ctx, TM_ERR_ARG, "internal: no reduction output");
@@ -851,7 +857,8 @@ void *odd_tmp(tm_ctx *ctx, int slot, const tm_gauge *g, int prec, int nrhs, int 
 //   sym^+:  t = R_oo^-+ D^+_oe R_ee^-+ x (twist on load); out = x - kappa^2 D^+_eo t
 // Over n problems at once; `fin` reduces |out|^2 per rhs.
 int mat_pc_batch(tm_ctx *ctx, const tm_gauge *const *g, void *const *out, const void *const *in,
-                 const int *nrhs, int n, int prec, int pc, int dagger, int fin, CGScalars *const *cg)
+                 const int *nrhs, int n, int prec, int pc, int dagger, int fin, CGScalars *const *cg,
+                 bool upd = false)
 {
     HopCall k1[kMaxProblems], k2[kMaxProblems];
     for (int i = 0; i < n; i++) {
@@ -862,7 +869,7 @@ int mat_pc_batch(tm_ctx *ctx, const tm_gauge *const *g, void *const *out, const 
         k1[i] = HopCall{g[i], prec, 1, dagger, 0, TM_EPI_TWINV, in[i], tmp, nullptr, 0.0, nrhs[i],
                         FIN_NONE, nullptr, nullptr};
         k2[i] = HopCall{g[i], prec, 0, dagger, 0, TM_EPI_RX_PLUS_KD, tmp, out[i], in[i], k2c, nrhs[i],
-                        fin, cg ? cg[i] : nullptr, nullptr};
+                        fin, cg ? cg[i] : nullptr, nullptr, upd ? 1 : 0};
         if (pc == TM_PC_SYM) {
             if (!dagger) {
                 k2[i].epi = TM_EPI_X_PLUS_K_TWINV_D;
@@ -951,6 +958,8 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (e) c->force_nr = atoi(e);
     e = getenv("TM_HOP_NT");
     if (e) c->force_nt = atoi(e) & 7;
+    e = getenv("TM_CG_FUSE");
+    if (e) c->cg_fuse = atoi(e) ? 1 : 0;
     e = getenv("TM_HOP_WCAP");
     if (e) c->force_wcap = std::min(8, std::max(0, atoi(e)));
     e = getenv("TM_TUNE");
@@ -1588,11 +1597,21 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
     }
 
     // One CG iteration over all problems, every stage one batched launch:
-    // M p (|M p|^2 -> alpha), M^+ M p, x += alpha p / r -= alpha A p (|r|^2 -> beta).
+    // M p (|M p|^2 -> alpha), then r -= alpha M^+ M p inside the last hop of
+    // M^+ (|r|^2 -> beta; A p is never stored) and x += alpha p.  With
+    // TM_CG_FUSE=0: A p stored, then one BLAS pass x += alpha p, r -= alpha A p.
     auto iteration_core = [&]() -> int {
         CGScalars *cgs[kMaxProblems];
         for (int i = 0; i < n; i++) cgs[i] = pr[i].cg;
         TM_TRY(mat_pc_batch(ctx, gs, mpv, (const void *const *)pv, nr, n, lp, pc, 0, FIN_ALPHA, cgs));
+        if (ctx->cg_fuse) {
+            TM_TRY(mat_pc_batch(ctx, gs, rv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_BETA, cgs, true));
+            BlasCall up[kMaxProblems];
+            for (int i = 0; i < n; i++)
+                up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg,
+                                 nullptr};
+            return launch_blas_batch(ctx, OP_X_UPDATE, xp, lp, nf, up, n);
+        }
         TM_TRY(mat_pc_batch(ctx, gs, apv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_NONE, nullptr));
         BlasCall up[kMaxProblems];
         for (int i = 0; i < n; i++)

@@ -39,7 +39,8 @@ enum BlasOp {
     OP_CONVERT = 3,     // v1 (PB) = scale v0 (PA)
     OP_ACCUM_ZERO = 4,  // v0 (PA) += v1 (PB); v1 = 0
     OP_NORM2 = 5,       // |v0|^2 (PA)
-    OP_DOT = 6          // <v0, v1> (PA), re / im
+    OP_DOT = 6,         // <v0, v1> (PA), re / im
+    OP_X_UPDATE = 7     // v0 (PA) += alpha v1 (PB): the solution step when the hop updated r
 };
 
 struct BlasProblem {

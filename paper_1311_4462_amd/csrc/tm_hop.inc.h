@@ -551,6 +551,18 @@ __device__ __forceinline__ void hop_epilogue(cx<typename Prec<P>::real> (&acc)[N
         else
             SpinorIO<P>::template store<false>(pb.out, pb.vh, vec, cb, A);
     };
+    // CG residual update (the solver's last hop of A p): the output holds r
+    // and becomes r - alpha A, so A p itself is never stored
+    auto update_out = [&](cx<real> *A, uint32_t vec, int rhs) {
+        const real al = (real)pb.upd[rhs].alpha;
+        cx<real> Rv[12];
+        if (nts & kNtOut)
+            SpinorIO<P>::template load<0, 12, true>(Rv, pb.out, pb.vh, vec, cb);
+        else
+            SpinorIO<P>::template load<0, 12, false>(Rv, pb.out, pb.vh, vec, cb);
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = Rv[k] - al * A[k];
+    };
     const real kk = (real)pb.k;
     const uint32_t vh = pb.vh;
     constexpr bool SPLIT = nd_split<NF>();
@@ -581,6 +593,7 @@ __device__ __forceinline__ void hop_epilogue(cx<typename Prec<P>::real> (&acc)[N
                     for (int k = 0; k < 12; k++) A[k] = T[k];
                 }
             }
+            if (pb.upd) update_out(A, (uint32_t)((r0 + r) * NF + fl), r0 + r);
             store_out(A, (uint32_t)((r0 + r) * NF + fl));
             if (pb.red.op != FIN_NONE) {
                 double s = 0.0;
@@ -617,6 +630,7 @@ __device__ __forceinline__ void hop_epilogue(cx<typename Prec<P>::real> (&acc)[N
             }
 #pragma unroll
             for (int f = 0; f < NF; f++) {
+                if (pb.upd) update_out(A[f], (uint32_t)((r0 + r) * NF + f), r0 + r);
                 store_out(A[f], (uint32_t)((r0 + r) * NF + f));
                 if (pb.red.op != FIN_NONE) {
                     double s = 0.0;

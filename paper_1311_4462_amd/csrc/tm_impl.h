@@ -974,6 +974,9 @@ struct HopProblem {
     const void *gauge[2];   // links of parity 0 / 1
     const void *clov;       // clover blocks of the output parity (twisted clover)
     SpinorPtr in, out, x;
+    // nullable: CG residual update in the epilogue, out = out - alpha A with
+    // A the epilogue's result and alpha of each rhs read from here
+    const CGScalars *upd;
     Reduce red;
 };
 

@@ -411,3 +411,57 @@ def test_wave_cap_one_block_per_cu(api, monkeypatch):
                     assert rel(from_native(api, c, out, p, prec, 0)[0], ref) < TOL[prec]
         g.close()
     c.close()
+
+
+@pytest.mark.parametrize("inner", [0, 1, 2, 3])
+def test_cg_fused_residual_update(api, inner, monkeypatch, tmp_path):
+    """The CG residual update inside the last hop of M^+ M p (r -= alpha A p
+    and |r|^2 in its epilogue, A p never stored) against the separate BLAS
+    pass (TM_CG_FUSE=0): both reach the 1e-10 residual the oracle recomputes
+    on every rhs, in the same number of iterations up to one, for the
+    doublet in both preconditionings and for a batch of two uneven
+    one-flavour lattices, with the tuner on (its trials must leave r alone)."""
+    dims = (6, 4, 4, 8)
+    pd = api.make_params(dims, 0.16, 0.13, 0.17, 2)
+    Ud = inputs.gauge_field(dims, "haar", 231)
+    bd = O.project(inputs.gaussian_spinor(dims, 2, 232, nrhs=2), dims, 0)
+    probs_dims = ((6, 4, 4, 8), (4, 6, 2, 6))
+    iters = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("TM_CG_FUSE", fuse)
+        monkeypatch.setenv("TM_TUNE", "1")
+        monkeypatch.setenv("TM_TUNE_CACHE", str(tmp_path / f"tune_{fuse}.txt"))
+        c = api.Context()
+        gd = api.Gauge(c, Ud, pd, precs=tuple(sorted({0, inner})))
+        tb = to_native(api, c, bd, pd, 0, 0, 2)
+        got = []
+        for pc in (0, 1):
+            x = api.new_field(pd, 0, 2)
+            res = api.tm_cg(c, x, tb, gd, pc=pc, tol=1e-10, inner=inner, nrhs=2)
+            xs = from_native(api, c, x, pd, 0, 0, 2)
+            for r in range(2):
+                assert res[r]["status"] == 0, (fuse, pc, r, res[r])
+                check_solve(oparams(pd), Ud, xs[r], bd[r], "asym" if pc == 0 else "sym",
+                            res[r]["true_rel_res_normal"])
+            got.append(res[0]["iters"])
+        gd.close()
+        probs = []
+        for i, d in enumerate(probs_dims):
+            pi = api.make_params(d, 0.15, 0.1, 0.0, 1)
+            Ui = inputs.gauge_field(d, "haar", 240 + i)
+            gi = api.Gauge(c, Ui, pi, precs=tuple(sorted({0, inner})))
+            bi = O.project(inputs.gaussian_spinor(d, 1, 250 + i, nrhs=3), d, 0)
+            probs.append((pi, Ui, gi, bi, to_native(api, c, bi, pi, 0, 0, 3), api.new_field(pi, 0, 3)))
+        res = api.tm_cg_batched(c, [q[2] for q in probs], [q[5] for q in probs], [q[4] for q in probs],
+                                [3] * len(probs), tol=1e-10, inner=inner)
+        for k, (pi, Ui, gi, bi, tbi, xi) in enumerate(probs):
+            xs = from_native(api, c, xi, pi, 0, 0, 3)
+            for r in range(3):
+                assert res[k * 3 + r]["status"] == 0, (fuse, k, r)
+                check_solve(oparams(pi), Ui, xs[r], bi[r], "asym", res[k * 3 + r]["true_rel_res_normal"])
+            gi.close()
+        got.append(res[0]["iters"])
+        iters[fuse] = got
+        c.close()
+    for a, b in zip(iters["1"], iters["0"]):
+        assert abs(a - b) <= 1, iters
