@@ -802,6 +802,7 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         switch (op) {
         case OP_CG_UPDATE: vp[1] = vp[2] = vp[3] = pb; break;
         case OP_X_UPDATE: vp[1] = pb; break;
+        case OP_XPAY_X: vp[1] = vp[2] = pb; break;
         case OP_XPAY: vp[0] = vp[1] = pb; break;
         case OP_RESIDUAL: vp[2] = vp[3] = pb; break;
         case OP_CONVERT: vp[1] = pb; break;
@@ -812,9 +813,10 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
             bp.v[j] = c.v[j] ? sptr(c.v[j], vp[j], c.vh, nf, c.nrhs) : SpinorPtr{nullptr, nullptr};
         bp.red.op = c.fin;
         bp.red.cg = c.cg;
-        // the CG update reads alpha and the xpay reads beta from the scalars
-        if ((op == OP_CG_UPDATE || op == OP_X_UPDATE || op == OP_XPAY || c.fin == FIN_ALPHA || c.fin == FIN_BETA ||
-             c.fin == FIN_STORE_RR || c.fin == FIN_RELIABLE) && !c.cg)
+        // the CG updates read alpha and the xpays beta from the scalars
+        const bool scalar_op = op == OP_CG_UPDATE || op == OP_X_UPDATE || op == OP_XPAY_X || op == OP_XPAY;
+        if ((scalar_op || c.fin == FIN_ALPHA || c.fin == FIN_BETA || c.fin == FIN_STORE_RR ||
+             c.fin == FIN_RELIABLE) && !c.cg)
             return fail(ctx, TM_ERR_ARG, "internal: BLAS op %d needs CG scalars", op);
         if (c.fin == FIN_STORE && !c.red_out) return fail(ctx, TM_ERR_ARG, "internal: no reduction output");
         if (c.fin != FIN_NONE) {
@@ -1598,35 +1600,48 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
 
     // One CG iteration over all problems, every stage one batched launch:
     // M p (|M p|^2 -> alpha), then r -= alpha M^+ M p inside the last hop of
-    // M^+ (|r|^2 -> beta; A p is never stored) and x += alpha p.  With
-    // TM_CG_FUSE=0: A p stored, then one BLAS pass x += alpha p, r -= alpha A p.
+    // M^+ (|r|^2 -> beta; A p is never stored); the step x += alpha p is
+    // taken by the pass that forms the next direction (xpay below).  With
+    // TM_CG_FUSE=0: A p stored, then one BLAS pass x += alpha p, r -= alpha A p,
+    // and the direction update alone.
     auto iteration_core = [&]() -> int {
         CGScalars *cgs[kMaxProblems];
         for (int i = 0; i < n; i++) cgs[i] = pr[i].cg;
         TM_TRY(mat_pc_batch(ctx, gs, mpv, (const void *const *)pv, nr, n, lp, pc, 0, FIN_ALPHA, cgs));
-        if (ctx->cg_fuse) {
-            TM_TRY(mat_pc_batch(ctx, gs, rv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_BETA, cgs, true));
-            BlasCall up[kMaxProblems];
-            for (int i = 0; i < n; i++)
-                up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg,
-                                 nullptr};
-            return launch_blas_batch(ctx, OP_X_UPDATE, xp, lp, nf, up, n);
-        }
+        if (ctx->cg_fuse)
+            return mat_pc_batch(ctx, gs, rv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_BETA, cgs, true);
         TM_TRY(mat_pc_batch(ctx, gs, apv, (const void *const *)mpv, nr, n, lp, pc, 1, FIN_NONE, nullptr));
         BlasCall up[kMaxProblems];
         for (int i = 0; i < n; i++)
             up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], rv[i], apv[i]}, FIN_BETA, pr[i].cg, nullptr};
         return launch_blas_batch(ctx, OP_CG_UPDATE, xp, lp, nf, up, n);
     };
-    // p = r + beta p (beta of the CG recurrence, or of a residual replacement)
+    // p = r + beta p (beta of the CG recurrence, or of a residual replacement),
+    // fused: x += alpha p first, from the same read of p (alpha is zero once
+    // a reliable update has taken the step)
     auto xpay = [&]() -> int {
         BlasCall xp_[kMaxProblems];
+        if (ctx->cg_fuse) {
+            for (int i = 0; i < n; i++)
+                xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], rv[i], nullptr}, FIN_NONE, pr[i].cg,
+                                  nullptr};
+            return launch_blas_batch(ctx, OP_XPAY_X, xp, lp, nf, xp_, n);
+        }
         for (int i = 0; i < n; i++)
             xp_[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {rv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg, nullptr};
         return launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n);
     };
     // reliable update: x += x_lo; r = c - A x in FP64 rounded into r_lo; beta = |r|^2 / |r_prev|^2
+    // (fused iterations: the step x_lo += alpha p is taken here first, and the
+    // residual replacement then sets alpha to zero for the xpay)
     auto reliable_update = [&]() -> int {
+        if (ctx->cg_fuse) {
+            BlasCall up[kMaxProblems];
+            for (int i = 0; i < n; i++)
+                up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg,
+                                 nullptr};
+            TM_TRY(launch_blas_batch(ctx, OP_X_UPDATE, xp, lp, nf, up, n));
+        }
         BlasCall acc[kMaxProblems];
         for (int i = 0; i < n; i++)
             acc[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, nullptr, nullptr}, FIN_NONE,

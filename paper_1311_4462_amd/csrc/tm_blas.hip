@@ -121,8 +121,8 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 
     double acc0 = 0.0, acc1 = 0.0;
     double alpha = 0.0, beta = 0.0;
-    if constexpr (OP == OP_CG_UPDATE || OP == OP_X_UPDATE) alpha = pb.red.cg[rhs].alpha;
-    if constexpr (OP == OP_XPAY) beta = pb.red.cg[rhs].beta;
+    if constexpr (OP == OP_CG_UPDATE || OP == OP_X_UPDATE || OP == OP_XPAY_X) alpha = pb.red.cg[rhs].alpha;
+    if constexpr (OP == OP_XPAY || OP == OP_XPAY_X) beta = pb.red.cg[rhs].beta;
 
     if constexpr (blas_flat<PA, PB>()) {
         constexpr int U = (PA == TM_FP64 && PB == TM_FP64) ? 1 : 2;
@@ -151,6 +151,10 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                 } else if constexpr (OP == OP_X_UPDATE) {
                     unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
                     unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
+                } else if constexpr (OP == OP_XPAY_X) {
+                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
+                    unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
+                    unit_load<PB, U>(a2[q], pb.v[2], rb, u, cbs[q], vh);
                 } else if constexpr (OP == OP_XPAY) {
                     unit_load<PB, U>(a0[q], pb.v[0], rb, u, cbs[q], vh);
                     unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
@@ -185,6 +189,14 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 #pragma unroll
                     for (int k = 0; k < U; k++) a0[q][k] = a0[q][k] + alpha * a1[q][k];
                     unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
+                } else if constexpr (OP == OP_XPAY_X) {      // x += alpha p, then p = r + beta p
+#pragma unroll
+                    for (int k = 0; k < U; k++) {
+                        a0[q][k] = a0[q][k] + alpha * a1[q][k];
+                        a1[q][k] = a2[q][k] + beta * a1[q][k];
+                    }
+                    unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
+                    unit_store<PB, U>(pb.v[1], rb, u, cb, vh, a1[q]);
                 } else if constexpr (OP == OP_XPAY) {        // p = r + beta p
 #pragma unroll
                     for (int k = 0; k < U; k++) a1[q][k] = a0[q][k] + beta * a1[q][k];
@@ -246,6 +258,18 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 #pragma unroll
                 for (int k = 0; k < 12; k++) x[k] = x[k] + alpha * p[k];
                 store_d<PA>(pb.v[0], vh, vec, cb, x);
+            } else if constexpr (OP == OP_XPAY_X) {
+                cx<double> x[12], p[12], r[12];
+                load_d<PA>(x, pb.v[0], vh, vec, cb);
+                load_d<PB>(p, pb.v[1], vh, vec, cb);
+                load_d<PB>(r, pb.v[2], vh, vec, cb);
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    x[k] = x[k] + alpha * p[k];
+                    p[k] = r[k] + beta * p[k];
+                }
+                store_d<PA>(pb.v[0], vh, vec, cb, x);
+                store_d<PB>(pb.v[1], vh, vec, cb, p);
             } else if constexpr (OP == OP_XPAY) {
                 cx<double> r[12], p[12];
                 load_d<PB>(r, pb.v[0], vh, vec, cb);
@@ -398,6 +422,11 @@ hipError_t launch_blas(int op, int pa, int pb, const BlasBatch &B, hipStream_t s
     TM_BL(OP_X_UPDATE, TM_FP32, TM_FP32)
     TM_BL(OP_X_UPDATE, TM_FP32, TM_FP16)
     TM_BL(OP_X_UPDATE, TM_FP32, TM_BF16)
+    // the step fused with the new direction
+    TM_BL(OP_XPAY_X, TM_FP64, TM_FP64)
+    TM_BL(OP_XPAY_X, TM_FP32, TM_FP32)
+    TM_BL(OP_XPAY_X, TM_FP32, TM_FP16)
+    TM_BL(OP_XPAY_X, TM_FP32, TM_BF16)
     TM_BL_SAME(OP_XPAY)
     TM_BL_ALL_B(OP_RESIDUAL, TM_FP64)
     TM_BL_ALL_B(OP_CONVERT, TM_FP64)

@@ -936,6 +936,9 @@ __device__ void finish_reduce(const Reduce &rd, int v0, int v1, int nblk, double
                     c.rr_upd = s;
                 }
                 c.beta = (c.rr_old > 0.0) ? s / c.rr_old : 0.0;
+                // the step alpha p of this iteration is in x already (taken
+                // before the replacement); a later pass of it adds nothing
+                c.alpha = 0.0;
                 c.rr = s;
                 c.maxrr = s;
                 c.active = (s > c.stop2) ? 1 : 0;
