@@ -269,8 +269,12 @@ int tm_reconstruct_odd(tm_ctx *ctx, void *x_o, const void *x_e, const void *b_o,
  * par->outer (TM_FP64), par->nrhs right-hand sides.  inner = TM_FP64: plain
  * FP64 CG; inner = FP32 / FP16 / BF16: mixed precision with reliable updates
  * (low-precision iterations; FP64 true residual, reductions and solution
- * accumulation).  res: array of par->nrhs results.  Synchronous.  Returns
- * TM_NOT_CONVERGED if some rhs missed tol within maxiter (x, res filled).     */
+ * accumulation).  An iteration updates the residual inside the last hop of
+ * M^+ M p (M^+ M p is not stored) and takes the step x += alpha p in the pass
+ * that forms the next direction; TM_CG_FUSE=0 in the environment at context
+ * creation selects separate passes instead (same arithmetic, more traffic).
+ * res: array of par->nrhs results.  Synchronous.  Returns TM_NOT_CONVERGED if
+ * some rhs missed tol within maxiter (x, res filled).                        */
 int tm_cg(tm_ctx *ctx, void *x_e, const void *b_e, const tm_gauge *g, const tm_cg_params *par,
           tm_cg_result *res);
 
