@@ -598,6 +598,16 @@ def main():
         "degenerate": {"double": 190, "single": 487, "half": 856},
         "non_degenerate": {"double": 163, "single": 516, "half": 879},
         "hardware": "NVIDIA GTX Titan (Kepler)"}
+    # what the reduced-precision figures in extra compute in
+    extra["dtype_notes"] = {
+        "f32": "FP32 storage and arithmetic (the headline)",
+        "f64": "FP64 storage and arithmetic",
+        "f16": "binary16 spinors and links with an FP32 scale per site; the projected half spinor is "
+               "formed in binary16 (packed adds, relative error about 3e-4 per hop), link products "
+               "accumulate in FP32 through two-term dot products, epilogues in FP32",
+        "bf16": "bfloat16 spinors and links with an FP32 scale per site; projection, link products and "
+                "epilogues in FP32",
+        "reductions": "every norm and dot product accumulates in FP64"}
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gflop/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(h["dt"] * 1e3, 5),
