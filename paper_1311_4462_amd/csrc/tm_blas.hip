@@ -341,16 +341,98 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
     }
 }
 
-// One block per (problem, vector): add the vector's partials in a fixed
-// order, then finish.
-__global__ void __launch_bounds__(256) finish_kernel(const FinishBatch F)
+// Final reduction of partials[v][0..nblk) for v in [v0, v1) by one block,
+// then the finishing operation.  Fixed summation order: each thread keeps
+// four running sums over strides of 4 BS (its loads independent, so they are
+// in flight together), then the block sum.
+template <int BS>
+__device__ void finish_reduce(const Reduce &rd, int v0, int v1, int nblk, double *sh)
 {
-    __shared__ double sh[4];
+    for (int v = v0; v < v1; v++) {
+        const double *part = rd.partials + (long)v * nblk;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int i = threadIdx.x;
+        for (; i + 3 * BS < nblk; i += 4 * BS) {
+            s0 += part[i];
+            s1 += part[i + BS];
+            s2 += part[i + 2 * BS];
+            s3 += part[i + 3 * BS];
+        }
+        for (; i < nblk; i += BS) s0 += part[i];
+        double s = block_sum<BS>((s0 + s1) + (s2 + s3), sh);
+        if (threadIdx.x == 0) {
+            if (rd.op == FIN_STORE) {
+                rd.out[v] = s;
+            } else if (rd.op == FIN_ALPHA) {
+                CGScalars &c = rd.cg[v];
+                c.pap = s;
+                c.alpha = (c.active && s > 0.0) ? c.rr / s : 0.0;
+            } else if (rd.op == FIN_BETA) {
+                CGScalars &c = rd.cg[v];
+                if (c.active) {
+                    c.beta = (c.rr > 0.0) ? s / c.rr : 0.0;
+                    c.rr_old = c.rr;
+                    c.rr = s;
+                    c.maxrr = fmax(c.maxrr, s);
+                    c.hist[c.niter % kHistory] = s;
+                    c.niter++;
+                    if (s <= c.stop2) {
+                        c.active = 0;
+                        c.pending = 1;
+                    }
+                } else {
+                    c.beta = 0.0;
+                }
+            } else if (rd.op == FIN_RELIABLE) {
+                // the residual was replaced by the true one (reliable update):
+                // continue the recurrence with beta = |r_true|^2 / |r_prev|^2
+                CGScalars &c = rd.cg[v];
+                // progress of the true residual from one replacement to the
+                // next, for rhs that were iterating (a converged rhs shares
+                // the replacements of the others without moving)
+                if (c.active || c.pending) {
+                    if (c.rr_upd > 0.0 && s >= c.stall_f2 * c.rr_upd)
+                        c.stall++;
+                    else
+                        c.stall = 0;
+                    c.rr_upd = s;
+                }
+                c.beta = (c.rr_old > 0.0) ? s / c.rr_old : 0.0;
+                // the step alpha p of this iteration is in x already (taken
+                // before the replacement); a later pass of it adds nothing
+                c.alpha = 0.0;
+                c.rr = s;
+                c.maxrr = s;
+                c.active = (s > c.stop2) ? 1 : 0;
+                c.pending = 0;
+            } else if (rd.op == FIN_STORE_RR) {
+                // a fresh residual: restart the recurrence for this rhs
+                CGScalars &c = rd.cg[v];
+                c.rr = s;
+                c.rr_old = s;
+                c.maxrr = s;
+                c.beta = 0.0;
+                c.active = (s > c.stop2) ? 1 : 0;
+                c.pending = 0;
+                c.rr_upd = s;
+                c.stall = 0;
+            }
+        }
+    }
+}
+
+// One block per (problem, vector): add the vector's partials in a fixed
+// order, then finish.  A hop launch leaves one partial per site block (16384
+// for 2^20 sites in blocks of 64), so the block is wide.
+constexpr int kFinishThreads = 1024;
+__global__ void __launch_bounds__(kFinishThreads) finish_kernel(const FinishBatch F)
+{
+    __shared__ double sh[kFinishThreads / 64];
     if (F.gate && *F.gate == 0) return;
     const Reduce &rd = F.r[blockIdx.x];
     const int v = (int)blockIdx.y;
     if (v >= rd.nvec) return;
-    finish_reduce<256>(rd, v, v + 1, rd.nblk, sh);
+    finish_reduce<kFinishThreads>(rd, v, v + 1, rd.nblk, sh);
 }
 
 __global__ void decide_kernel(const DecideArgs D)
@@ -396,7 +478,7 @@ hipError_t launch_finish(const FinishBatch &F, hipStream_t st)
 {
     int nv = 1;
     for (int i = 0; i < F.nprob; i++) nv = std::max(nv, F.r[i].nvec);
-    hipLaunchKernelGGL(finish_kernel, dim3(F.nprob, nv), dim3(256), 0, st, F);
+    hipLaunchKernelGGL(finish_kernel, dim3(F.nprob, nv), dim3(kFinishThreads), 0, st, F);
     return hipGetLastError();
 }
 

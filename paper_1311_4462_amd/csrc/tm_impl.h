@@ -889,76 +889,6 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return s;
 }
 
-// Final reduction of partials[v][0..nblk) for v in [v0, v1) by one block,
-// then the finishing operation.  Fixed summation order.
-template <int BS>
-__device__ void finish_reduce(const Reduce &rd, int v0, int v1, int nblk, double *sh)
-{
-    for (int v = v0; v < v1; v++) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += BS) s += rd.partials[(long)v * nblk + i];
-        s = block_sum<BS>(s, sh);
-        if (threadIdx.x == 0) {
-            if (rd.op == FIN_STORE) {
-                rd.out[v] = s;
-            } else if (rd.op == FIN_ALPHA) {
-                CGScalars &c = rd.cg[v];
-                c.pap = s;
-                c.alpha = (c.active && s > 0.0) ? c.rr / s : 0.0;
-            } else if (rd.op == FIN_BETA) {
-                CGScalars &c = rd.cg[v];
-                if (c.active) {
-                    c.beta = (c.rr > 0.0) ? s / c.rr : 0.0;
-                    c.rr_old = c.rr;
-                    c.rr = s;
-                    c.maxrr = fmax(c.maxrr, s);
-                    c.hist[c.niter % kHistory] = s;
-                    c.niter++;
-                    if (s <= c.stop2) {
-                        c.active = 0;
-                        c.pending = 1;
-                    }
-                } else {
-                    c.beta = 0.0;
-                }
-            } else if (rd.op == FIN_RELIABLE) {
-                // the residual was replaced by the true one (reliable update):
-                // continue the recurrence with beta = |r_true|^2 / |r_prev|^2
-                CGScalars &c = rd.cg[v];
-                // progress of the true residual from one replacement to the
-                // next, for rhs that were iterating (a converged rhs shares
-                // the replacements of the others without moving)
-                if (c.active || c.pending) {
-                    if (c.rr_upd > 0.0 && s >= c.stall_f2 * c.rr_upd)
-                        c.stall++;
-                    else
-                        c.stall = 0;
-                    c.rr_upd = s;
-                }
-                c.beta = (c.rr_old > 0.0) ? s / c.rr_old : 0.0;
-                // the step alpha p of this iteration is in x already (taken
-                // before the replacement); a later pass of it adds nothing
-                c.alpha = 0.0;
-                c.rr = s;
-                c.maxrr = s;
-                c.active = (s > c.stop2) ? 1 : 0;
-                c.pending = 0;
-            } else if (rd.op == FIN_STORE_RR) {
-                // a fresh residual: restart the recurrence for this rhs
-                CGScalars &c = rd.cg[v];
-                c.rr = s;
-                c.rr_old = s;
-                c.maxrr = s;
-                c.beta = 0.0;
-                c.active = (s > c.stop2) ? 1 : 0;
-                c.pending = 0;
-                c.rr_upd = s;
-                c.stall = 0;
-            }
-        }
-    }
-}
-
 // ------------------------------------------------------------------ hop descriptors
 
 struct HopProblem {
