@@ -301,10 +301,11 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(inputs, U3, U2, b2, with_c2_cg=False):
+def cpu_baseline(inputs, U3, U2, b2, with_c2_cg=False, with_c3_cg=False):
     """The FP64 oracle on this host: the asymmetric operator at 24^3 x 48
     (degenerate) and 32^3 x 64 (doublet) on one thread and on all threads,
-    and a full FP64 CG (tiny 4^4 lattice; 24^3 x 48 on request)."""
+    and a full FP64 CG (tiny 4^4 lattice; 24^3 x 48 and the 32^3 x 64 doublet
+    on request)."""
     from oracle import oracle as O
     runs = []
     nthreads = O.num_threads()
@@ -330,22 +331,30 @@ def cpu_baseline(inputs, U3, U2, b2, with_c2_cg=False):
     op3 = O.Params(HEADLINE_DIMS, HEADLINE["kappa"], HEADLINE["mu"], HEADLINE["eps"], O.NDEG)
     b3e = O.project(inputs.gaussian_spinor(HEADLINE_DIMS, 2, 2003), HEADLINE_DIMS, 0)
     apply_runs("mat_pc_asym_32x32x32x64_nd", op3, U3, b3e, FLOPS_PER_SITE["nd"] * 1048576, 3)
-    del b3e
-    # full FP64 CG on the tiny lattice (Haar links, kappa = 0.160, mu = 0.01)
-    cgs = [((4, 4, 4, 4), "haar", 1001, 0.160, 0.01, "sym")]
+    # full FP64 CG: the tiny lattice (Haar links, kappa = 0.160, mu = 0.01),
+    # on request 24^3 x 48 and the 32^3 x 64 doublet of the GPU comparison
+    cgs = [("4x4x4x4_deg_sym", O.Params((4, 4, 4, 4), 0.160, 0.01, 0.0, O.PLUS),
+            lambda: inputs.gauge_field((4, 4, 4, 4), "haar", 1001),
+            lambda: O.project(inputs.gaussian_spinor((4, 4, 4, 4), 1, 2001), (4, 4, 4, 4), 0), "sym")]
     if with_c2_cg:
-        cgs.append((dims2, None, None, 0.1615, 0.004, "asym"))
-    for dims, kind, seed, kappa, mu, pc in cgs:
-        op = O.Params(dims, kappa, mu, 0.0, O.PLUS)
-        U = U2 if kind is None else inputs.gauge_field(dims, kind, seed)
-        b = b2e if kind is None else O.project(inputs.gaussian_spinor(dims, 1, 2001), dims, 0)
+        cgs.append(("24x24x24x48_deg_asym", op2, lambda: U2, lambda: b2e, "asym"))
+    if with_c3_cg:
+        cgs.append(("32x32x32x64_nd_asym", op3, lambda: U3, lambda: b3e, "asym"))
+    for tag, op, getU, getb, pc in cgs:
+        U, b = getU(), getb()
         t0 = time.perf_counter()
-        _, info = O.cg(op, U, b, pc, tol=1e-10)
+
+        def progress(it, rel, tag=tag):
+            if it % 5 == 0:
+                log(f"cpu baseline cg {tag}: iteration {it}, |r|/|c| = {rel:.2e}")
+
+        _, info = O.cg(op, U, b, pc, tol=1e-10, progress=progress)
         t = time.perf_counter() - t0
-        runs.append({"run": f"cg_fp64_{'x'.join(map(str, dims))}_deg_{pc}", "threads": nthreads,
+        runs.append({"run": f"cg_fp64_{tag}", "threads": nthreads,
                      "seconds": round(t, 3), "iters": info["iters"],
                      "true_rel_res_normal": info["true_rel_res_normal"]})
-        log(f"cpu baseline cg {dims}: {t:.2f} s, {info['iters']} iterations")
+        log(f"cpu baseline cg {tag}: {t:.2f} s, {info['iters']} iterations")
+    del b3e
     head = [r for r in runs if r["run"] == "mat_pc_asym_32x32x32x64_nd" and r["threads"] == nthreads][0]
     return {"value": head["gflops"], "unit": "Gflop/s", "cores": nthreads, "kind": "oracle",
             "cpu_model": cpu_model(),
@@ -491,6 +500,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cg-24", action="store_true",
                     help="also time a full FP64 oracle CG at 24^3x48 (about a minute of CPU)")
+    ap.add_argument("--cpu-cg-32", action="store_true",
+                    help="also time a full FP64 oracle CG on the 32^3x64 doublet (several minutes of CPU)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only the oracle runs on the host (no GPU work), as one JSON line")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--headline-only", action="store_true",
@@ -507,6 +520,16 @@ def main():
               "the lattice in t and exchange the spin-projected faces between neighbours).",
               file=sys.stderr)
         sys.exit(2)
+
+    if a.cpu_only:
+        from paper_1311_4462_amd import inputs
+        log("bench: generating links")
+        U3 = inputs.gauge_field(HEADLINE_DIMS, "near_unit", 1003)
+        U2 = inputs.gauge_field((24, 24, 24, 48), "near_unit", 1002)
+        b2 = inputs.gaussian_spinor((24, 24, 24, 48), 1, 2002)
+        print(json.dumps({"cpu_baseline": cpu_baseline(inputs, U3, U2, b2, a.cpu_cg_24, a.cpu_cg_32)}),
+              flush=True)
+        return
 
     import torch
 
@@ -587,7 +610,7 @@ def main():
             extra.update(force_section(torch, api, inputs))
         if not a.no_cpu_baseline:
             log("cpu baseline: oracle runs")
-            cpu = cpu_baseline(inputs, U3, U2, b2, a.cpu_cg_24)
+            cpu = cpu_baseline(inputs, U3, U2, b2, a.cpu_cg_24, a.cpu_cg_32)
         del U2, b2
     del U3
 

@@ -261,11 +261,13 @@ def _nrm2(a):
     return float(np.vdot(a, a).real)
 
 
-def cg(p: Params, U, b_e, pc="asym", tol=1e-10, maxiter=10000, x0=None):
+def cg(p: Params, U, b_e, pc="asym", tol=1e-10, maxiter=10000, x0=None, progress=None):
     """CG on M^+ M x = M^+ b in FP64 (normal equations, even sites).
 
     Stops when the true residual |M^+ b - M^+ M x| <= tol |M^+ b|.  Returns
     (x, info) with info = dict(iters, true_rel_res_normal, true_rel_res_pc).
+    progress: optional callable(iteration, |r| / |M^+ b|) after each iteration
+    (output for long runs; it takes no part in the arithmetic).
     """
     c = mat_pc(p, U, b_e, pc, dagger=True)
     x = np.zeros_like(b_e) if x0 is None else x0.copy()
@@ -291,6 +293,8 @@ def cg(p: Params, U, b_e, pc="asym", tol=1e-10, maxiter=10000, x0=None):
         pdir = r + (rr_new / rr) * pdir
         rr = rr_new
         it += 1
+        if progress is not None:
+            progress(it, np.sqrt(rr / cc))
     rn = np.sqrt(_nrm2(c - normal_op(p, U, x, pc)) / cc)
     rp = np.sqrt(_nrm2(b_e - mat_pc(p, U, x, pc)) / _nrm2(b_e))
     return x, dict(iters=it, true_rel_res_normal=rn, true_rel_res_pc=rp)
