@@ -807,6 +807,7 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         case OP_RESIDUAL: vp[2] = vp[3] = pb; break;
         case OP_CONVERT: vp[1] = pb; break;
         case OP_ACCUM_ZERO: vp[1] = pb; break;
+        case OP_ACCUM_STEP: vp[1] = TM_FP32; vp[2] = pb; break;
         default: break;
         }
         for (int j = 0; j < 4; j++)
@@ -814,7 +815,8 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         bp.red.op = c.fin;
         bp.red.cg = c.cg;
         // the CG updates read alpha and the xpays beta from the scalars
-        const bool scalar_op = op == OP_CG_UPDATE || op == OP_X_UPDATE || op == OP_XPAY_X || op == OP_XPAY;
+        const bool scalar_op = op == OP_CG_UPDATE || op == OP_X_UPDATE || op == OP_XPAY_X || op == OP_XPAY ||
+                               op == OP_ACCUM_STEP;
         if ((scalar_op || c.fin == FIN_ALPHA || c.fin == FIN_BETA || c.fin == FIN_STORE_RR ||
              c.fin == FIN_RELIABLE) && !c.cg)
             return fail(ctx, TM_ERR_ARG, "internal: BLAS op %d needs CG scalars", op);
@@ -1632,15 +1634,17 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         return launch_blas_batch(ctx, OP_XPAY, lp, lp, nf, xp_, n);
     };
     // reliable update: x += x_lo; r = c - A x in FP64 rounded into r_lo; beta = |r|^2 / |r_prev|^2
-    // (fused iterations: the step x_lo += alpha p is taken here first, and the
-    // residual replacement then sets alpha to zero for the xpay)
+    // (fused iterations: the step of this iteration goes into x here as well,
+    // x += x_lo + alpha p, and the residual replacement then sets alpha to
+    // zero for the xpay)
     auto reliable_update = [&]() -> int {
         if (ctx->cg_fuse) {
             BlasCall up[kMaxProblems];
             for (int i = 0; i < n; i++)
-                up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {xv[i], pv[i], nullptr, nullptr}, FIN_NONE, pr[i].cg,
-                                 nullptr};
-            TM_TRY(launch_blas_batch(ctx, OP_X_UPDATE, xp, lp, nf, up, n));
+                up[i] = BlasCall{pr[i].g->vh, pr[i].nrhs, {pr[i].x, pr[i].xlo, pv[i], nullptr}, FIN_NONE,
+                                 pr[i].cg, nullptr};
+            TM_TRY(launch_blas_batch(ctx, OP_ACCUM_STEP, TM_FP64, lp, nf, up, n));
+            return true_residual(ctx, pr, pc, lp, rv, nullptr, FIN_RELIABLE);
         }
         BlasCall acc[kMaxProblems];
         for (int i = 0; i < n; i++)

@@ -121,7 +121,8 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 
     double acc0 = 0.0, acc1 = 0.0;
     double alpha = 0.0, beta = 0.0;
-    if constexpr (OP == OP_CG_UPDATE || OP == OP_X_UPDATE || OP == OP_XPAY_X) alpha = pb.red.cg[rhs].alpha;
+    if constexpr (OP == OP_CG_UPDATE || OP == OP_X_UPDATE || OP == OP_XPAY_X || OP == OP_ACCUM_STEP)
+        alpha = pb.red.cg[rhs].alpha;
     if constexpr (OP == OP_XPAY || OP == OP_XPAY_X) beta = pb.red.cg[rhs].beta;
 
     if constexpr (blas_flat<PA, PB>()) {
@@ -166,6 +167,10 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                 } else if constexpr (OP == OP_ACCUM_ZERO) {
                     unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
                     unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
+                } else if constexpr (OP == OP_ACCUM_STEP) {  // PB = FP32 here: x_lo and p alike
+                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
+                    unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
+                    unit_load<PB, U>(a2[q], pb.v[2], rb, u, cbs[q], vh);
                 } else if constexpr (OP == OP_DOT) {
                     unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
                     unit_load<PA, U>(a1[q], pb.v[1], ra, u, cbs[q], vh);
@@ -217,6 +222,14 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 #pragma unroll
                     for (int k = 0; k < U; k++) {
                         a0[q][k] = a0[q][k] + a1[q][k];
+                        a1[q][k] = mk(0.0, 0.0);
+                    }
+                    unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
+                    unit_store<PB, U>(pb.v[1], rb, u, cb, vh, a1[q]);
+                } else if constexpr (OP == OP_ACCUM_STEP) {  // y += x + alpha p, x = 0
+#pragma unroll
+                    for (int k = 0; k < U; k++) {
+                        a0[q][k] = a0[q][k] + (a1[q][k] + alpha * a2[q][k]);
                         a1[q][k] = mk(0.0, 0.0);
                     }
                     unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
@@ -306,6 +319,19 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                 }
                 store_d<PA>(pb.v[0], vh, vec, cb, y);
                 store_d<PB>(pb.v[1], vh, vec, cb, x);
+            } else if constexpr (OP == OP_ACCUM_STEP) {
+                // x_lo is FP32 whatever the direction's format PB
+                cx<double> y[12], x[12], p[12];
+                load_d<PA>(y, pb.v[0], vh, vec, cb);
+                load_d<TM_FP32>(x, pb.v[1], vh, vec, cb);
+                load_d<PB>(p, pb.v[2], vh, vec, cb);
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    y[k] = y[k] + (x[k] + alpha * p[k]);
+                    x[k] = mk(0.0, 0.0);
+                }
+                store_d<PA>(pb.v[0], vh, vec, cb, y);
+                store_d<TM_FP32>(pb.v[1], vh, vec, cb, x);
             } else if constexpr (OP == OP_NORM2) {
                 cx<double> a[12];
                 load_d<PA>(a, pb.v[0], vh, vec, cb);
@@ -517,6 +543,9 @@ hipError_t launch_blas(int op, int pa, int pb, const BlasBatch &B, hipStream_t s
     TM_BL_ALL_B(OP_CONVERT, TM_BF16)
     TM_BL(OP_ACCUM_ZERO, TM_FP64, TM_FP32)
     TM_BL(OP_ACCUM_ZERO, TM_FP64, TM_FP64)
+    TM_BL(OP_ACCUM_STEP, TM_FP64, TM_FP32)
+    TM_BL(OP_ACCUM_STEP, TM_FP64, TM_FP16)
+    TM_BL(OP_ACCUM_STEP, TM_FP64, TM_BF16)
     TM_BL_SAME(OP_NORM2)
     TM_BL_SAME(OP_DOT)
     return hipErrorInvalidConfiguration;
