@@ -801,7 +801,6 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         int vp[4] = {pa, pa, pa, pa};
         switch (op) {
         case OP_CG_UPDATE: vp[1] = vp[2] = vp[3] = pb; break;
-        case OP_X_UPDATE: vp[1] = pb; break;
         case OP_XPAY_X: vp[1] = vp[2] = pb; break;
         case OP_XPAY: vp[0] = vp[1] = pb; break;
         case OP_RESIDUAL: vp[2] = vp[3] = pb; break;
@@ -815,8 +814,7 @@ int launch_blas_batch(tm_ctx *ctx, int op, int pa, int pb, int nf, const BlasCal
         bp.red.op = c.fin;
         bp.red.cg = c.cg;
         // the CG updates read alpha and the xpays beta from the scalars
-        const bool scalar_op = op == OP_CG_UPDATE || op == OP_X_UPDATE || op == OP_XPAY_X || op == OP_XPAY ||
-                               op == OP_ACCUM_STEP;
+        const bool scalar_op = op == OP_CG_UPDATE || op == OP_XPAY_X || op == OP_XPAY || op == OP_ACCUM_STEP;
         if ((scalar_op || c.fin == FIN_ALPHA || c.fin == FIN_BETA || c.fin == FIN_STORE_RR ||
              c.fin == FIN_RELIABLE) && !c.cg)
             return fail(ctx, TM_ERR_ARG, "internal: BLAS op %d needs CG scalars", op);

@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
 
     double acc0 = 0.0, acc1 = 0.0;
     double alpha = 0.0, beta = 0.0;
-    if constexpr (OP == OP_CG_UPDATE || OP == OP_X_UPDATE || OP == OP_XPAY_X || OP == OP_ACCUM_STEP)
+    if constexpr (OP == OP_CG_UPDATE || OP == OP_XPAY_X || OP == OP_ACCUM_STEP)
         alpha = pb.red.cg[rhs].alpha;
     if constexpr (OP == OP_XPAY || OP == OP_XPAY_X) beta = pb.red.cg[rhs].beta;
 
@@ -149,9 +149,6 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                     unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
                     unit_load<PB, U>(a2[q], pb.v[2], rb, u, cbs[q], vh);
                     unit_load<PB, U>(a3[q], pb.v[3], rb, u, cbs[q], vh);
-                } else if constexpr (OP == OP_X_UPDATE) {
-                    unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
-                    unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
                 } else if constexpr (OP == OP_XPAY_X) {
                     unit_load<PA, U>(a0[q], pb.v[0], ra, u, cbs[q], vh);
                     unit_load<PB, U>(a1[q], pb.v[1], rb, u, cbs[q], vh);
@@ -190,10 +187,6 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                     unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
                     unit_store<PB, U>(pb.v[2], rb, u, cb, vh, a2[q]);
                     acc0 += unit_nrm2<U>(a2[q]);
-                } else if constexpr (OP == OP_X_UPDATE) {    // x += alpha p
-#pragma unroll
-                    for (int k = 0; k < U; k++) a0[q][k] = a0[q][k] + alpha * a1[q][k];
-                    unit_store<PA, U>(pb.v[0], ra, u, cb, vh, a0[q]);
                 } else if constexpr (OP == OP_XPAY_X) {      // x += alpha p, then p = r + beta p
 #pragma unroll
                     for (int k = 0; k < U; k++) {
@@ -264,13 +257,6 @@ __global__ void __launch_bounds__(BS) blas_kernel(const BlasBatch B)
                 store_d<PA>(pb.v[0], vh, vec, cb, x);
                 store_d<PB>(pb.v[2], vh, vec, cb, r);
                 acc0 += nrm2_12(r);
-            } else if constexpr (OP == OP_X_UPDATE) {
-                cx<double> x[12], p[12];
-                load_d<PA>(x, pb.v[0], vh, vec, cb);
-                load_d<PB>(p, pb.v[1], vh, vec, cb);
-#pragma unroll
-                for (int k = 0; k < 12; k++) x[k] = x[k] + alpha * p[k];
-                store_d<PA>(pb.v[0], vh, vec, cb, x);
             } else if constexpr (OP == OP_XPAY_X) {
                 cx<double> x[12], p[12], r[12];
                 load_d<PA>(x, pb.v[0], vh, vec, cb);
@@ -525,12 +511,7 @@ hipError_t launch_blas(int op, int pa, int pb, const BlasBatch &B, hipStream_t s
     TM_BL(OP_CG_UPDATE, TM_FP32, TM_FP32)
     TM_BL(OP_CG_UPDATE, TM_FP32, TM_FP16)
     TM_BL(OP_CG_UPDATE, TM_FP32, TM_BF16)
-    // the same solution step alone (the residual was updated by the hop)
-    TM_BL(OP_X_UPDATE, TM_FP64, TM_FP64)
-    TM_BL(OP_X_UPDATE, TM_FP32, TM_FP32)
-    TM_BL(OP_X_UPDATE, TM_FP32, TM_FP16)
-    TM_BL(OP_X_UPDATE, TM_FP32, TM_BF16)
-    // the step fused with the new direction
+    // with the residual updated by the hop: the step fused with the new direction
     TM_BL(OP_XPAY_X, TM_FP64, TM_FP64)
     TM_BL(OP_XPAY_X, TM_FP32, TM_FP32)
     TM_BL(OP_XPAY_X, TM_FP32, TM_FP16)

@@ -40,7 +40,6 @@ enum BlasOp {
     OP_ACCUM_ZERO = 4,  // v0 (PA) += v1 (PB); v1 = 0
     OP_NORM2 = 5,       // |v0|^2 (PA)
     OP_DOT = 6,         // <v0, v1> (PA), re / im
-    OP_X_UPDATE = 7,    // v0 (PA) += alpha v1 (PB): the solution step when the hop updated r
     OP_XPAY_X = 8,      // v0 (PA) += alpha v1; v1 = v2 + beta v1  (v1, v2: PB): step and new direction
     OP_ACCUM_STEP = 9   // v0 (PA) += v1 (FP32) + alpha v2 (PB); v1 = 0: a reliable update's solution
 };
