@@ -476,15 +476,20 @@ def force_section(torch, api, inputs):
     F = torch.empty(U.shape, dtype=torch.complex64, device="cuda")
     t = time_launches(torch, lambda: api.tm_force(ctx, F, api.FP32, xb, g, api.FP32, api.ASYM, 1.0, False, None), 20)
     vh = (dims[0] * dims[1] * dims[2] * dims[3]) // 2
-    Ur = U.clone().requires_grad_(True)
-    torch.cuda.synchronize(); t0 = time.perf_counter()
-    S = tm_action(Ur, phi, p)
-    S.backward()
-    torch.cuda.synchronize(); t_ag = time.perf_counter() - t0
+    # one action + gradient step; the first call also tunes the launches of
+    # the solves' shapes, the second is timed as well
+    t_ag = []
+    for _ in range(2):
+        Ur = U.clone().requires_grad_(True)
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        S = tm_action(Ur, phi, p)
+        S.backward()
+        torch.cuda.synchronize(); t_ag.append(time.perf_counter() - t0)
     g.close(); ctx.close()
     return {"force_16x16x16x32_nd": {"tm_force_fp32_us": round(t * 1e6, 1),
                                       "note": "tm_force = M X, two hops for Z and W, and the outer-product kernel",
-                                      "autograd_forward_backward_s": round(t_ag, 4),
+                                      "autograd_forward_backward_s": round(t_ag[1], 4),
+                                      "autograd_forward_backward_first_call_s": round(t_ag[0], 4),
                                       "links": 4 * 2 * vh}}
 
 
