@@ -476,8 +476,8 @@ def force_section(torch, api, inputs):
     F = torch.empty(U.shape, dtype=torch.complex64, device="cuda")
     t = time_launches(torch, lambda: api.tm_force(ctx, F, api.FP32, xb, g, api.FP32, api.ASYM, 1.0, False, None), 20)
     vh = (dims[0] * dims[1] * dims[2] * dims[3]) // 2
-    # one action + gradient step; the first call also tunes the launches of
-    # the solves' shapes, the second is timed as well
+    # one action + gradient step, twice: the first call also creates the
+    # autograd context and its workspaces
     t_ag = []
     for _ in range(2):
         Ur = U.clone().requires_grad_(True)
