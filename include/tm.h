@@ -273,6 +273,8 @@ int tm_reconstruct_odd(tm_ctx *ctx, void *x_o, const void *x_e, const void *b_o,
  * M^+ M p (M^+ M p is not stored) and takes the step x += alpha p in the pass
  * that forms the next direction; TM_CG_FUSE=0 in the environment at context
  * creation selects separate passes instead (same arithmetic, more traffic).
+ * TM_VERBOSE=1 (read at context creation) prints the progress at every host
+ * check and each rhs's final residuals to stderr.
  * res: array of par->nrhs results.  Synchronous.  Returns TM_NOT_CONVERGED if
  * some rhs missed tol within maxiter (x, res filled).                        */
 int tm_cg(tm_ctx *ctx, void *x_e, const void *b_e, const tm_gauge *g, const tm_cg_params *par,

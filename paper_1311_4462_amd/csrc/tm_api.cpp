@@ -61,6 +61,7 @@ struct tm_ctx {
     int force_nr = 0;                  // TM_HOP_NR: 1, 2 or 4 rhs per thread where instantiated (0: default)
     int force_nt = -1;                 // TM_HOP_NT: non-temporal stream mask of the hop launches (see HopCfg)
     int cg_fuse = 1;                   // TM_CG_FUSE=0: CG residual update as a separate BLAS pass
+    int verbose = 0;                   // TM_VERBOSE=1: solver progress on stderr
     const int *gate = nullptr;         // set while enqueuing gated (device-decided) launches
     int xcd_remap = 1;
     unsigned lds_per_cu = 0;           // from the runtime at context creation
@@ -962,6 +963,8 @@ int tm_ctx_create(tm_ctx **ctx, void *hip_stream)
     if (e) c->force_nt = atoi(e) & 7;
     e = getenv("TM_CG_FUSE");
     if (e) c->cg_fuse = atoi(e) ? 1 : 0;
+    e = getenv("TM_VERBOSE");
+    if (e) c->verbose = atoi(e);
     e = getenv("TM_HOP_WCAP");
     if (e) c->force_wcap = std::min(8, std::max(0, atoi(e)));
     e = getenv("TM_TUNE");
@@ -1829,6 +1832,20 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
         const int prev = slot ^ 1;
         TM_HIP(ctx, hipEventSynchronize(snap_ev[prev]));
         unpack(prev);
+        if (ctx->verbose) {
+            // the largest iterated residual over the rhs still iterating
+            double worst = 0.0;
+            int live = 0;
+            for (int i = 0; i < n; i++)
+                for (int r = 0; r < pr[i].nrhs; r++) {
+                    const CGScalars &s = sc[i][r];
+                    if (!(s.active || (mixed && s.pending))) continue;
+                    live++;
+                    if (pr[i].cc[r] > 0) worst = std::max(worst, std::sqrt(s.rr / pr[i].cc[r]));
+                }
+            fprintf(stderr, "tm_cg: %d iterations, %d reliable updates, %d rhs iterating, max |r|/|c| %.3e\n",
+                    hflags[3], mixed ? hflags[1] : 0, live, worst);
+        }
         bool bad = false, stall = false;
         for (int i = 0; i < n; i++)
             for (int r = 0; r < pr[i].nrhs; r++) {
@@ -1965,6 +1982,10 @@ int cg_run(tm_ctx *ctx, std::vector<CGProblem> &pr, const tm_cg_params *par, tm_
             }
             if (!std::isfinite(o.true_rel_res_normal)) status = fail(ctx, TM_ERR_NAN, "non-finite residual");
             if (status == TM_OK && o.true_rel_res_normal > par->tol * 1.0000001) status = TM_NOT_CONVERGED;
+            if (ctx->verbose)
+                fprintf(stderr, "tm_cg: problem %d rhs %d: %d iterations, %d reliable updates, true |r|/|c| "
+                        "%.3e (preconditioned system %.3e), %.4f s\n",
+                        i, r, o.iters, o.reliable_updates, o.true_rel_res_normal, o.true_rel_res_pc, o.seconds);
         }
     return status;
 }

@@ -465,3 +465,28 @@ def test_cg_fused_residual_update(api, inner, monkeypatch, tmp_path):
         c.close()
     for a, b in zip(iters["1"], iters["0"]):
         assert abs(a - b) <= 1, iters
+
+
+def test_verbose_solver_log(api, monkeypatch, capfd):
+    """TM_VERBOSE=1: the solver prints its progress at every host check and
+    the final residuals of each rhs to stderr (the values it returns)."""
+    monkeypatch.setenv("TM_VERBOSE", "1")
+    dims = (4, 4, 4, 4)
+    p = api.make_params(dims, 0.16, 0.01, 0.0, 1)
+    U = inputs.gauge_field(dims, "haar", 261)
+    c = api.Context()
+    g = api.Gauge(c, U, p, precs=(0, 2))
+    b = O.project(inputs.gaussian_spinor(dims, 1, 262), dims, 0)
+    tb = to_native(api, c, b, p, 0, 0)
+    x = api.new_field(p, 0)
+    res = api.tm_cg(c, x, tb, g, pc=1, tol=1e-10, inner=2)[0]
+    g.close()
+    c.close()
+    err = capfd.readouterr().err
+    assert res["status"] == 0
+    progress = [l for l in err.splitlines() if l.startswith("tm_cg: ") and "rhs iterating" in l]
+    assert progress, err
+    final = [l for l in err.splitlines() if l.startswith("tm_cg: problem 0 rhs 0:")]
+    assert len(final) == 1, err
+    assert f"{res['iters']} iterations, {res['reliable_updates']} reliable updates" in final[0]
+    assert f"{res['true_rel_res_normal']:.3e}" in final[0]
