@@ -490,3 +490,26 @@ def test_verbose_solver_log(api, monkeypatch, capfd):
     assert len(final) == 1, err
     assert f"{res['iters']} iterations, {res['reliable_updates']} reliable updates" in final[0]
     assert f"{res['true_rel_res_normal']:.3e}" in final[0]
+
+
+def _small_mixed_problem(api, c, seed):
+    dims = (6, 4, 4, 8)
+    p = api.make_params(dims, 0.16, 0.1, 0.0, 1)
+    U = inputs.gauge_field(dims, "haar", seed)
+    g = api.Gauge(c, U, p, precs=(0, 1, 2))
+    b = O.project(inputs.gaussian_spinor(dims, 1, seed + 1), dims, 0)
+    return p, U, g, b, to_native(api, c, b, p, 0, 0)
+
+
+def test_precision_fallback_after_stalls(api, ctx):
+    """A mixed solve whose reliable updates make no progress (here every
+    update counts as a stall: stall_factor 1e-12) continues from its x with
+    the next wider inner format after max_stalls of them, and still reaches
+    1e-10 as the oracle recomputes."""
+    p, U, g, b, tb = _small_mixed_problem(api, ctx, 281)
+    x = api.new_field(p, 0)
+    res = api.tm_cg(ctx, x, tb, g, pc=0, tol=1e-10, inner=2, stall_factor=1e-12, max_stalls=1)[0]
+    g.close()
+    assert res["status"] == 0, res
+    assert res["precision_fallbacks"] >= 1, res
+    check_solve(oparams(p), U, from_native(api, ctx, x, p, 0, 0)[0], b, "asym", res["true_rel_res_normal"])
