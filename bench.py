@@ -590,8 +590,9 @@ def main():
         extra["rates_32x32x32x64"]["deg"] = kernel_rates(torch, api, ctx, gd, pd, (api.FP32,), 20,
                                                          FLOPS_PER_SITE["deg_asym"])
         gd.close()
-        g8 = api.Gauge(ctx, Ut, p, recon=8, precs=(api.FP32, api.FP16))
-        extra["rates_32x32x32x64"]["nd_recon8"] = kernel_rates(torch, api, ctx, g8, p, (api.FP32, api.FP16), 20,
+        g8 = api.Gauge(ctx, Ut, p, recon=8, precs=(api.FP64, api.FP32, api.FP16))
+        extra["rates_32x32x32x64"]["nd_recon8"] = kernel_rates(torch, api, ctx, g8, p,
+                                                               (api.FP64, api.FP32, api.FP16), 20,
                                                                FLOPS_PER_SITE["nd"], recon=8)
         g8.close()
         log(f"32^3x64 rates: {extra['rates_32x32x32x64']}")
