@@ -107,7 +107,8 @@ typedef enum {
 } tm_epilogue;
 
 typedef struct {
-    int dims[4];          /* Lx, Ly, Lz, Lt: even, >= 2                         */
+    int dims[4];          /* Lx, Ly, Lz, Lt: even, >= 2; at most 2e8 sites per
+                             parity (TM_ERR_LIMIT beyond: 32-bit site indices) */
     double kappa;         /* hopping parameter                                  */
     double mu;            /* bare twisted mass of Eq. (2.1) (lattice units)      */
     double epsilon;       /* bare flavour splitting of Eq. (2.1); doublet only   */

@@ -68,6 +68,13 @@ def test_validation_without_device(L):
     assert L.tm_gauge_create(h, ctypes.byref(g), dummy, ctypes.byref(p), 12, 3) == -1
     assert L.tm_mat_pc(h, dummy, dummy, None, 0, 0, 0, 1) == -1
     assert L.tm_cg(h, dummy, dummy, None, None, None) == -1
+    # the largest lattice: 2e8 sites per parity (site indices stay 32-bit)
+    p.flavor, p.kappa, p.mu, p.epsilon = 1, 0.16, 0.1, 0.0
+    for i, d in enumerate((1024, 1024, 512, 2)):
+        p.dims[i] = d
+    assert L.tm_gauge_create(h, ctypes.byref(g), dummy, ctypes.byref(p), 12, 3) == -9
+    assert b"too large" in L.tm_last_error(h)
+    assert L.tm_spinor_bytes(ctypes.byref(p), 0, 1) == 0
     assert L.tm_ctx_destroy(h) == 0
 
 
