@@ -513,3 +513,30 @@ def test_precision_fallback_after_stalls(api, ctx):
     assert res["status"] == 0, res
     assert res["precision_fallbacks"] >= 1, res
     check_solve(oparams(p), U, from_native(api, ctx, x, p, 0, 0)[0], b, "asym", res["true_rel_res_normal"])
+
+
+@pytest.mark.parametrize("inner", [0, 2])
+def test_zero_source(api, ctx, inner):
+    """A zero source is solved by x = 0 with a zero residual; in a batch it
+    stays zero (its alpha and beta are zero) while the other sources
+    converge as the oracle recomputes, and alone it takes no iteration."""
+    dims = (6, 4, 4, 8)
+    p = api.make_params(dims, 0.16, 0.1, 0.0, 1)
+    U = inputs.gauge_field(dims, "haar", 291)
+    g = api.Gauge(ctx, U, p, precs=tuple(sorted({0, inner})))
+    b = O.project(inputs.gaussian_spinor(dims, 1, 292, nrhs=3), dims, 0)
+    b[1] = 0
+    tb = to_native(api, ctx, b, p, 0, 0, 3)
+    x = api.new_field(p, 0, 3)
+    res = api.tm_cg(ctx, x, tb, g, pc=0, tol=1e-10, inner=inner, nrhs=3)
+    xs = from_native(api, ctx, x, p, 0, 0, 3)
+    assert np.all(xs[1] == 0) and res[1]["true_rel_res_normal"] == 0.0, res[1]
+    for r in (0, 2):
+        assert res[r]["status"] == 0
+        check_solve(oparams(p), U, xs[r], b[r], "asym", res[r]["true_rel_res_normal"])
+    t0 = to_native(api, ctx, b[1:2], p, 0, 0, 1)
+    x0 = api.new_field(p, 0)
+    r0 = api.tm_cg(ctx, x0, t0, g, pc=0, tol=1e-10, inner=inner)[0]
+    assert r0["status"] == 0 and r0["iters"] == 0 and r0["true_rel_res_normal"] == 0.0, r0
+    assert np.all(from_native(api, ctx, x0, p, 0, 0)[0] == 0)
+    g.close()
