@@ -516,6 +516,9 @@ def main():
     ap.add_argument("--cg-only", action="store_true", help="only the 32^3x64 CG comparison")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the operator-variant, batched and force sections")
+    ap.add_argument("--no-24", action="store_true",
+                    help="only the 32^3x64 sections: skip the 24^3x48 one and what follows it "
+                         "(batched sources, force, CPU baseline)")
     ap.add_argument("--cg-reps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
@@ -609,7 +612,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if not a.headline_only:
+    if not a.headline_only and not a.no_24:
         extra["deg_24x24x24x48"], U2, b2 = section_24(torch, api, inputs, a)
         if not a.no_batch:
             extra["batched"] = batched_section(torch, api, inputs)
