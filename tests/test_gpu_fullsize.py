@@ -122,21 +122,22 @@ def test_c3_mat_pc_recon8(api, ctx, c3):
     g8.close()
 
 
-@pytest.mark.parametrize("inner", [0, 2, 3])
-def test_c3_cg_to_1e10(api, ctx, c3, inner):
-    """FP64 CG and mixed (FP16 / BF16 storage, FP32 arithmetic, FP64 reliable
-    updates) reach a 1e-10 true residual on the doublet, checked by the oracle."""
+@pytest.mark.parametrize("inner,pc", [(0, 0), (1, 0), (2, 0), (3, 0), (2, 1)])
+def test_c3_cg_to_1e10(api, ctx, c3, inner, pc):
+    """FP64 CG and mixed (FP32 / FP16 / BF16 storage, FP32 arithmetic, FP64
+    reliable updates) reach a 1e-10 true residual on the doublet, checked by
+    the oracle; asymmetric preconditioning, and symmetric for FP16."""
     p, U, g, b = c3
     op = oparams(p)
     be = O.project(b, op.dims, 0)
     tb = to_native(api, ctx, be, p, 0, 0)
     tx = api.new_field(p, 0)
-    res = api.tm_cg(ctx, tx, tb, g, pc=0, tol=1e-10, inner=inner)[0]
+    res = api.tm_cg(ctx, tx, tb, g, pc=pc, tol=1e-10, inner=inner)[0]
     assert res["status"] == 0 and res["true_rel_res_normal"] <= 1e-10, res
     if inner != 0:
         assert res["reliable_updates"] >= 1
     xe = from_native(api, ctx, tx, p, 0, 0)[0]
-    check_solve(op, U, xe, be, "asym", res["true_rel_res_normal"])
+    check_solve(op, U, xe, be, "asym" if pc == 0 else "sym", res["true_rel_res_normal"])
 
 
 def test_c4a_sixteen_sources(api, ctx, c2):
