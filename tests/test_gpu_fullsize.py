@@ -140,15 +140,16 @@ def test_c3_cg_to_1e10(api, ctx, c3, inner, pc):
     check_solve(op, U, xe, be, "asym" if pc == 0 else "sym", res["true_rel_res_normal"])
 
 
-def test_c4a_sixteen_sources(api, ctx, c2):
-    """16 Z2 sources on 24^3 x 48 in one batched solve; every rhs reaches 1e-10,
-    recomputed by the oracle."""
+@pytest.mark.parametrize("inner", [1, 2])
+def test_c4a_sixteen_sources(api, ctx, c2, inner):
+    """16 Z2 sources on 24^3 x 48 in one batched mixed solve (FP32 or FP16
+    inner iterations); every rhs reaches 1e-10, recomputed by the oracle."""
     p, U, g, _ = c2
     op = oparams(p)
     b = O.project(inputs.z2_spinor(op.dims, 1, 2004, nrhs=16), op.dims, 0)
     tb = to_native(api, ctx, b, p, 0, 0, 16)
     tx = api.new_field(p, 0, 16)
-    res = api.tm_cg(ctx, tx, tb, g, pc=0, tol=1e-10, inner=1, nrhs=16)
+    res = api.tm_cg(ctx, tx, tb, g, pc=0, tol=1e-10, inner=inner, nrhs=16)
     assert all(r["true_rel_res_normal"] <= 1e-10 for r in res)
     x = from_native(api, ctx, tx, p, 0, 0, 16)
     for r in range(16):
